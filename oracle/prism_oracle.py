@@ -94,7 +94,8 @@ class Problem:
 
     @property
     def M(self):
-        return float(self.V if self.norm_count is None else self.norm_count)
+        # an empty group has only empty sums; any finite |M| leaves them at zero
+        return float(max(self.V, 1) if self.norm_count is None else self.norm_count)
 
     @property
     def C(self):

@@ -1,0 +1,636 @@
+// Host side of libprism: argument validation, problem planning (mask
+// compaction, neighbour tables, work items, reduction tiles), workspace
+// sizing and kernel dispatch.  Implements the C ABI declared in prism.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/prism.h"
+#include "prism_internal.h"
+
+using namespace prism;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PRISM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Bucket {
+  int K, mode, learn_d, maxN;
+  int item_begin, item_count;
+};
+
+}  // namespace
+
+struct prism_problem {
+  int device = 0;
+  ModelDev model{};
+  prism_launch launch{};
+  std::vector<prism_group_desc> desc;       // mask pointers are not kept
+  std::vector<GroupDev> groups;
+  std::vector<ItemDev> items;
+  std::vector<Bucket> buckets;
+  std::vector<TileDev> tiles;
+  std::vector<int32_t> tri_groups;
+  std::vector<int32_t> acq_off;
+  int max_field_chunks = 0;
+  int64_t n_vox = 0, n_micro = 0, n_cal = 0, n_y = 0;
+  size_t ws_rec = 0, ws_part = 0, ws_float = 0;  // element counts
+  // device tables
+  GroupDev* d_groups = nullptr;
+  ItemDev* d_items = nullptr;
+  TileDev* d_tiles = nullptr;
+  float* d_bval = nullptr;
+  float* d_bvec = nullptr;
+  int32_t* d_coords = nullptr;
+  int32_t* d_nbr = nullptr;
+  int32_t* d_grid = nullptr;
+  int32_t* d_tri = nullptr;
+  // optional timing of the fused kernel
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  mutable int ev_used = 0;
+
+  void free_plan() {
+    (void)hipFree(d_items);
+    (void)hipFree(d_tiles);
+    d_items = nullptr;
+    d_tiles = nullptr;
+  }
+  ~prism_problem() {
+    free_plan();
+    (void)hipFree(d_groups);
+    (void)hipFree(d_bval);
+    (void)hipFree(d_bvec);
+    (void)hipFree(d_coords);
+    (void)hipFree(d_nbr);
+    (void)hipFree(d_grid);
+    (void)hipFree(d_tri);
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int n_bias_of(int bias) { return bias == PRISM_BIAS_POLY2 ? 10 : bias == PRISM_BIAS_TRILINEAR8 ? 512 : 0; }
+
+// Work items, buckets and reduction tiles for the current launch shape.
+int plan(prism_problem* h) {
+  const prism_launch& L = h->launch;
+  const int rows = 4 / L.n_split;
+  const int chunk = 64 * L.vox_per_lane * rows;
+  int item_vox = L.item_vox;
+  if (item_vox <= 0) {
+    // about six blocks per compute unit over the whole problem, whole chunks
+    const int64_t target = 256 * 6;
+    int64_t per = (h->n_vox + target - 1) / target;
+    per = ((per + chunk - 1) / chunk) * chunk;
+    item_vox = (int)std::max<int64_t>(chunk, std::min<int64_t>(per, 8 * chunk));
+  }
+  if (item_vox % chunk != 0)
+    return fail(PRISM_E_INVALID, "item_vox %d is not a multiple of the block chunk %d", item_vox, chunk);
+
+  std::vector<ItemDev> items;
+  std::vector<std::vector<int>> per_group(h->groups.size());
+  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+    GroupDev& g = h->groups[gi];
+    int rec = 0;
+    for (int v0 = 0; v0 < g.V; v0 += item_vox) {
+      ItemDev it;
+      it.group = (int)gi;
+      it.v0 = v0;
+      it.nv = std::min(item_vox, g.V - v0);
+      it.rec = rec++;
+      per_group[gi].push_back((int)items.size());
+      items.push_back(it);
+    }
+    g.item_count = rec;
+  }
+  // buckets by kernel variant; items inside a bucket largest-first (LPT)
+  std::vector<Bucket> buckets;
+  std::vector<ItemDev> ordered;
+  ordered.reserve(items.size());
+  std::vector<bool> done(h->groups.size(), false);
+  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+    if (done[gi]) continue;
+    const GroupDev& g0 = h->groups[gi];
+    Bucket b{g0.K, g0.mode, g0.learn_d, 0, (int)ordered.size(), 0};
+    std::vector<ItemDev> bi;
+    for (size_t gj = gi; gj < h->groups.size(); ++gj) {
+      const GroupDev& g = h->groups[gj];
+      if (done[gj] || g.K != b.K || g.mode != b.mode || g.learn_d != b.learn_d) continue;
+      done[gj] = true;
+      b.maxN = std::max(b.maxN, g.N);
+      for (int ii : per_group[gj]) bi.push_back(items[ii]);
+    }
+    std::stable_sort(bi.begin(), bi.end(), [&](const ItemDev& a, const ItemDev& c) {
+      const int64_t ca = (int64_t)a.nv * h->groups[a.group].N;
+      const int64_t cc = (int64_t)c.nv * h->groups[c.group].N;
+      return ca > cc;
+    });
+    ordered.insert(ordered.end(), bi.begin(), bi.end());
+    b.item_count = (int)bi.size();
+    if (b.item_count > 0) buckets.push_back(b);
+  }
+  // records and first-stage reduction tiles
+  std::vector<TileDev> tiles;
+  int64_t rec_off = 0;
+  int max_fc = 0;
+  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+    GroupDev& g = h->groups[gi];
+    g.rec_off = rec_off;
+    rec_off += (int64_t)g.item_count * g.rec_stride;
+    const int nrr = (g.item_count + 63) / 64;
+    const int nfc = (g.rec_stride + 63) / 64;
+    max_fc = std::max(max_fc, nfc);
+    g.tile_begin = (int)tiles.size();
+    g.tile_count = nrr * nfc;
+    for (int fc = 0; fc < nfc; ++fc)
+      for (int rr = 0; rr < nrr; ++rr) {
+        TileDev t;
+        t.group = (int)gi;
+        t.r0 = rr * 64;
+        t.nr = std::min(64, g.item_count - rr * 64);
+        t.f0 = fc * 64;
+        t.nf = std::min(64, g.rec_stride - fc * 64);
+        t.out = (int)tiles.size() * 64;
+        tiles.push_back(t);
+      }
+  }
+  h->free_plan();
+  h->items = ordered;
+  h->buckets = buckets;
+  h->tiles = tiles;
+  h->max_field_chunks = max_fc;
+  h->ws_rec = (size_t)rec_off;
+  h->ws_part = tiles.size() * 64;
+  hipError_t e = upload(&h->d_items, h->items);
+  if (e == hipSuccess) e = upload(&h->d_tiles, h->tiles);
+  if (e == hipSuccess) {
+    (void)hipFree(h->d_groups);
+    h->d_groups = nullptr;
+    e = upload(&h->d_groups, h->groups);
+  }
+  if (e != hipSuccess) return fail(PRISM_E_ALLOC, "device upload failed: %s", hipGetErrorString(e));
+  return PRISM_OK;
+}
+
+int check_launch(const prism_launch* L) {
+  if (L->vox_per_lane != 1 && L->vox_per_lane != 2)
+    return fail(PRISM_E_INVALID, "vox_per_lane must be 1 or 2 (got %d)", L->vox_per_lane);
+  if (L->n_split != 1 && L->n_split != 2 && L->n_split != 4)
+    return fail(PRISM_E_INVALID, "n_split must be 1, 2 or 4 (got %d)", L->n_split);
+  if (L->item_vox < 0) return fail(PRISM_E_INVALID, "item_vox must be >= 0");
+  return PRISM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t prism_abi_version(void) { return PRISM_ABI_VERSION; }
+
+const char* prism_last_error(void) { return g_last_error.c_str(); }
+
+void prism_model_defaults(prism_model* m) {
+  if (!m) return;
+  m->d_csf = 3.0f;
+  m->d_gm = 0.9f;
+  m->d_res = 0.2f;
+  m->d_par = 1.7f;
+  m->d_perp = 0.4f;
+  m->lam_sp = 0.01f;
+  m->huber_delta = 0.05f;
+  m->lam_rep = 0.01f;
+  m->lam_sparse = 0.02f;
+  m->tau_sparse = 0.15f;
+  m->lam_alpha = 0.01f;
+  m->lam_beta = 0.01f;
+  m->lam_bias = 0.01f;
+}
+
+int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups, int32_t n_groups,
+                             const prism_acq* acqs, int32_t n_acq, const prism_model* model) {
+  if (!out) return fail(PRISM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!groups || n_groups <= 0) return fail(PRISM_E_INVALID, "need at least one group");
+  if (!acqs || n_acq <= 0) return fail(PRISM_E_INVALID, "need at least one acquisition");
+  if (!model) return fail(PRISM_E_INVALID, "model is NULL");
+  const float mv[] = {model->d_csf, model->d_gm, model->d_res, model->d_par, model->d_perp,
+                      model->lam_sp, model->huber_delta, model->lam_rep, model->lam_sparse,
+                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias};
+  for (float x : mv)
+    if (!std::isfinite(x) || x < 0.0f) return fail(PRISM_E_INVALID, "model constants must be finite and >= 0");
+  // acquisitions
+  std::vector<int32_t> acq_off(n_acq);
+  std::vector<float> bval, bvec;
+  for (int a = 0; a < n_acq; ++a) {
+    const prism_acq& q = acqs[a];
+    if (q.n_meas < 1 || q.n_meas > PRISM_MAX_MEAS)
+      return fail(PRISM_E_INVALID, "acquisition %d: n_meas %d outside 1..%d", a, q.n_meas, PRISM_MAX_MEAS);
+    if (!q.bval || !q.bvec) return fail(PRISM_E_INVALID, "acquisition %d: NULL bval or bvec", a);
+    acq_off[a] = (int32_t)bval.size();
+    for (int n = 0; n < q.n_meas; ++n) {
+      const float b = q.bval[n];
+      const float gx = q.bvec[3 * n], gy = q.bvec[3 * n + 1], gz = q.bvec[3 * n + 2];
+      if (!std::isfinite(b) || b < 0.0f)
+        return fail(PRISM_E_INVALID, "acquisition %d: b-value %d is negative or not finite", a, n);
+      if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz))
+        return fail(PRISM_E_INVALID, "acquisition %d: direction %d not finite", a, n);
+      const float nrm = std::sqrt(gx * gx + gy * gy + gz * gz);
+      if (b > 0.0f && std::fabs(nrm - 1.0f) > 1e-3f)
+        return fail(PRISM_E_INVALID, "acquisition %d: direction %d is not a unit vector (|g| = %g)", a, n, nrm);
+      bval.push_back(b);
+      bvec.push_back(gx);
+      bvec.push_back(gy);
+      bvec.push_back(gz);
+    }
+  }
+  prism_problem* h = new (std::nothrow) prism_problem();
+  if (!h) return fail(PRISM_E_ALLOC, "host allocation failed");
+  (void)hipGetDevice(&h->device);
+  h->model = ModelDev{model->d_csf, model->d_gm, model->d_res, model->d_par, model->d_perp,
+                      model->lam_sp, model->huber_delta, model->lam_rep, model->lam_sparse,
+                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias};
+  std::vector<int32_t> coords, nbr, grid;
+  int64_t micro = 0, cal = 0, y = 0, vox = 0, wfl = 0;
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const prism_group_desc& d = groups[gi];
+    auto bad = [&](const char* what) {
+      delete h;
+      return fail(PRISM_E_INVALID, "group %d: %s", gi, what);
+    };
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1 || d.nx > PRISM_MAX_EDGE || d.ny > PRISM_MAX_EDGE || d.nz > PRISM_MAX_EDGE)
+      return bad("box edges must be in 1..1023");
+    if (d.K < 1 || d.K > PRISM_MAX_K) return bad("K must be in 1..6");
+    if (d.mode != PRISM_MSE && d.mode != PRISM_RICIAN) return bad("unknown data mode");
+    if (d.bias != PRISM_BIAS_NONE && d.bias != PRISM_BIAS_POLY2 && d.bias != PRISM_BIAS_TRILINEAR8)
+      return bad("unknown bias basis");
+    if (d.acq < 0 || d.acq >= n_acq) return bad("acquisition index out of range");
+    if (d.neighbourhood != 0 && d.neighbourhood != 6 && d.neighbourhood != 26)
+      return bad("neighbourhood must be 0, 6 or 26");
+    if (d.learn_diffusivity != 0 && d.learn_diffusivity != 1) return bad("learn_diffusivity must be 0 or 1");
+    if (d.priors & ~0xFu) return bad("unknown prior bits");
+    const int64_t box = (int64_t)d.nx * d.ny * d.nz;
+    if (box > (int64_t)1 << 31) return bad("box too large");
+    // compaction in raster order
+    std::vector<int32_t> idx;
+    const bool need_idx = d.neighbourhood != 0 || d.bias == PRISM_BIAS_TRILINEAR8;
+    if (need_idx) idx.assign((size_t)box, -1);
+    int32_t V = 0;
+    const size_t cbase = coords.size();
+    for (int i = 0; i < d.nx; ++i)
+      for (int j = 0; j < d.ny; ++j)
+        for (int k = 0; k < d.nz; ++k) {
+          const int64_t r = ((int64_t)i * d.ny + j) * d.nz + k;
+          if (d.mask && !d.mask[r]) continue;
+          if (need_idx) idx[(size_t)r] = V;
+          coords.push_back(i | (j << 10) | (k << 20));
+          ++V;
+        }
+    GroupDev g{};
+    g.micro_off = micro;
+    g.cal_off = cal;
+    g.y_off = y;
+    g.vox_off = (int64_t)cbase;
+    g.V = V;
+    g.N = acqs[d.acq].n_meas;
+    g.K = d.K;
+    g.C = d.K + 3;
+    g.P = 4 * d.K + 5 + (d.learn_diffusivity ? 2 : 0);
+    g.mode = d.mode;
+    g.bias = d.bias;
+    g.n_bias = n_bias_of(d.bias);
+    g.learn_d = d.learn_diffusivity;
+    g.nbh = d.neighbourhood;
+    g.priors = (int32_t)d.priors;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.nz = d.nz;
+    g.acq_off = acq_off[d.acq];
+    g.rec_stride = kRecHead + 2 * g.N;
+    g.invM = V > 0 ? 1.0f / (float)V : 0.0f;
+    g.nbr_off = (int64_t)nbr.size();
+    if (d.neighbourhood != 0) {
+      std::vector<int> off;
+      for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+          for (int c = -1; c <= 1; ++c) {
+            const int m = std::abs(a) + std::abs(b) + std::abs(c);
+            if (m == 0 || (d.neighbourhood == 6 && m != 1)) continue;
+            off.push_back(a);
+            off.push_back(b);
+            off.push_back(c);
+          }
+      const int nq = (int)off.size() / 3;
+      const size_t nb0 = nbr.size();
+      nbr.resize(nb0 + (size_t)nq * V, -1);
+      for (int32_t v = 0; v < V; ++v) {
+        const int32_t pc = coords[cbase + v];
+        const int i = pc & 1023, j = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
+        for (int q = 0; q < nq; ++q) {
+          const int a = i + off[3 * q], b = j + off[3 * q + 1], c = k + off[3 * q + 2];
+          if (a < 0 || b < 0 || c < 0 || a >= d.nx || b >= d.ny || c >= d.nz) continue;
+          nbr[nb0 + (size_t)q * V + v] = idx[((size_t)a * d.ny + b) * d.nz + c];
+        }
+      }
+    }
+    g.grid_off = (int64_t)grid.size();
+    if (d.bias == PRISM_BIAS_TRILINEAR8) {
+      grid.insert(grid.end(), idx.begin(), idx.end());
+      h->tri_groups.push_back(gi);
+    }
+    g.w_off = wfl;
+    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += (int64_t)g.C * V;
+    g.glb_off = wfl;
+    if (d.bias == PRISM_BIAS_TRILINEAR8) wfl += V;
+    micro += (int64_t)g.P * V;
+    cal += g.n_bias + 2 * g.N + 1;
+    y += (int64_t)g.N * V;
+    vox += V;
+    h->groups.push_back(g);
+    prism_group_desc dc = d;
+    dc.mask = nullptr;
+    h->desc.push_back(dc);
+  }
+  h->n_vox = vox;
+  h->n_micro = micro;
+  h->n_cal = cal;
+  h->n_y = y;
+  h->ws_float = (size_t)wfl;
+  h->acq_off = acq_off;
+  // default launch shape: split measurements across waves for small problems
+  h->launch.vox_per_lane = 1;
+  h->launch.n_split = vox < 65536 ? 4 : (vox < 262144 ? 2 : 1);
+  h->launch.item_vox = 0;
+  hipError_t e = upload(&h->d_bval, bval);
+  if (e == hipSuccess) e = upload(&h->d_bvec, bvec);
+  if (e == hipSuccess) e = upload(&h->d_coords, coords);
+  if (e == hipSuccess) e = upload(&h->d_nbr, nbr);
+  if (e == hipSuccess) e = upload(&h->d_grid, grid);
+  if (e == hipSuccess) e = upload(&h->d_tri, h->tri_groups);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(PRISM_E_ALLOC, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  int rc = plan(h);
+  if (rc != PRISM_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return PRISM_OK;
+}
+
+int32_t prism_problem_destroy(prism_problem* h) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  delete h;
+  return PRISM_OK;
+}
+
+int32_t prism_problem_info(const prism_problem* h, prism_problem_info_t* info) {
+  if (!h || !info) return fail(PRISM_E_INVALID, "NULL argument");
+  info->n_vox = h->n_vox;
+  info->n_micro = h->n_micro;
+  info->n_cal = h->n_cal;
+  info->n_y = h->n_y;
+  info->n_groups = (int32_t)h->groups.size();
+  info->n_buckets = (int32_t)h->buckets.size();
+  return PRISM_OK;
+}
+
+int32_t prism_group_info(const prism_problem* h, int32_t group, prism_group_info_t* info) {
+  if (!h || !info) return fail(PRISM_E_INVALID, "NULL argument");
+  if (group < 0 || group >= (int32_t)h->groups.size()) return fail(PRISM_E_INVALID, "group %d out of range", group);
+  const GroupDev& g = h->groups[group];
+  info->n_vox = g.V;
+  info->n_meas = g.N;
+  info->K = g.K;
+  info->n_params_vox = g.P;
+  info->n_bias = g.n_bias;
+  info->n_cal = g.n_bias + 2 * g.N + 1;
+  info->pad = 0;
+  info->micro_offset = g.micro_off;
+  info->cal_offset = g.cal_off;
+  info->y_offset = g.y_off;
+  return PRISM_OK;
+}
+
+int32_t prism_problem_tune(prism_problem* h, const prism_launch* launch) {
+  if (!h || !launch) return fail(PRISM_E_INVALID, "NULL argument");
+  int rc = check_launch(launch);
+  if (rc != PRISM_OK) return rc;
+  const prism_launch old = h->launch;
+  h->launch = *launch;
+  rc = plan(h);
+  if (rc != PRISM_OK) {
+    h->launch = old;
+    plan(h);
+  }
+  return rc;
+}
+
+int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch) {
+  if (!h || !launch) return fail(PRISM_E_INVALID, "NULL argument");
+  *launch = h->launch;
+  return PRISM_OK;
+}
+
+int32_t prism_workspace_bytes(const prism_problem* h, size_t* bytes) {
+  if (!h || !bytes) return fail(PRISM_E_INVALID, "NULL argument");
+  *bytes = align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)) +
+           align256(h->ws_float * sizeof(float));
+  return PRISM_OK;
+}
+
+static PassArgs pass_args(const prism_problem* h, const float* y, const float* tm, const float* tc,
+                          float* gm, double* rec, float* wsp, uint32_t* status) {
+  PassArgs a{};
+  a.groups = h->d_groups;
+  a.items = h->d_items;
+  a.bval = h->d_bval;
+  a.bvec = h->d_bvec;
+  a.coords = h->d_coords;
+  a.nbr = h->d_nbr;
+  a.y = y;
+  a.th_micro = tm;
+  a.th_cal = tc;
+  a.g_micro = gm;
+  a.rec = rec;
+  a.wsp = wsp;
+  a.status = status;
+  a.model = h->model;
+  a.n_split = h->launch.n_split;
+  return a;
+}
+
+int32_t prism_synthesize(const prism_problem* h, const float* theta_micro, const float* theta_cal,
+                         float* yhat, void* stream) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  if ((h->n_micro && !theta_micro) || !theta_cal || (h->n_y && !yhat))
+    return fail(PRISM_E_INVALID, "NULL device pointer");
+  hipStream_t s = (hipStream_t)stream;
+  PassArgs a = pass_args(h, nullptr, theta_micro, theta_cal, nullptr, nullptr, nullptr, nullptr);
+  a.synth_only = 1;
+  a.yhat = yhat;
+  for (const Bucket& b : h->buckets) {
+    a.item_base = b.item_begin;
+    a.n_items = b.item_count;
+    hipError_t e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, 1, b.maxN, s);
+    if (e != hipSuccess) return hip_fail(e, "synthesis launch");
+  }
+  return PRISM_OK;
+}
+
+int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* theta_micro,
+                        const float* theta_cal, double* loss, float* grad_micro, float* grad_cal,
+                        void* workspace, size_t workspace_bytes, uint32_t* status, void* stream) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  if ((h->n_y && !y) || (h->n_micro && (!theta_micro || !grad_micro)) || !theta_cal || !grad_cal ||
+      !loss || !status)
+    return fail(PRISM_E_INVALID, "NULL device pointer");
+  size_t need = 0;
+  prism_workspace_bytes(h, &need);
+  if (need > 0 && !workspace) return fail(PRISM_E_INVALID, "workspace is NULL");
+  if (workspace_bytes < need)
+    return fail(PRISM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  double* rec = (double*)ws;
+  double* part = (double*)(ws + align256(h->ws_rec * sizeof(double)));
+  float* wsp = (float*)(ws + align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)));
+  PassArgs a = pass_args(h, y, theta_micro, theta_cal, grad_micro, rec, wsp, status);
+  hipError_t e = hipSuccess;
+  if (!h->items.empty()) {
+    a.item_base = 0;
+    a.n_items = (int)h->items.size();
+    e = launch_spatial(a, (int)h->items.size(), s);
+    if (e != hipSuccess) return hip_fail(e, "spatial-prior launch");
+  }
+  for (const Bucket& b : h->buckets) {
+    a.item_base = b.item_begin;
+    a.n_items = b.item_count;
+    const bool timed = h->prof && h->ev_used + 2 <= (int)h->ev.size();
+    if (timed) (void)hipEventRecord(h->ev[h->ev_used], s);
+    e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, h->launch.vox_per_lane, b.maxN, s);
+    if (e != hipSuccess) return hip_fail(e, "fused-pass launch");
+    if (timed) {
+      (void)hipEventRecord(h->ev[h->ev_used + 1], s);
+      h->ev_used += 2;
+    }
+  }
+  ReduceArgs r{};
+  r.groups = h->d_groups;
+  r.tiles = h->d_tiles;
+  r.rec = rec;
+  r.part = part;
+  r.th_cal = theta_cal;
+  r.g_cal = grad_cal;
+  r.loss = loss;
+  r.wsp = wsp;
+  r.grid = h->d_grid;
+  r.coords = h->d_coords;
+  r.status = status;
+  r.model = h->model;
+  r.n_tiles = (int)h->tiles.size();
+  r.n_groups = (int)h->groups.size();
+  e = launch_reduce(r, h->max_field_chunks, s);
+  if (e != hipSuccess) return hip_fail(e, "reduction launch");
+  e = launch_bias_trilinear(r, h->d_tri, (int)h->tri_groups.size(), s);
+  if (e != hipSuccess) return hip_fail(e, "trilinear-bias launch");
+  return PRISM_OK;
+}
+
+int32_t prism_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t* step, void* stream) {
+  if (n < 0) return fail(PRISM_E_INVALID, "n must be >= 0");
+  if (!step || (n > 0 && (!p || !g || !m || !v))) return fail(PRISM_E_INVALID, "NULL device pointer");
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+    return fail(PRISM_E_INVALID, "Adam hyper-parameters out of range");
+  hipError_t e = launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "Adam launch");
+  return PRISM_OK;
+}
+
+int32_t prism_rprop_step(float* p, const float* g, float* prev, float* step, int64_t n,
+                         float eta_minus, float eta_plus, float step_min, float step_max,
+                         void* stream) {
+  if (n < 0) return fail(PRISM_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!p || !g || !prev || !step)) return fail(PRISM_E_INVALID, "NULL device pointer");
+  if (!(eta_minus > 0.0f && eta_minus < 1.0f) || !(eta_plus > 1.0f) || !(step_min >= 0.0f) ||
+      !(step_max >= step_min))
+    return fail(PRISM_E_INVALID, "Rprop hyper-parameters out of range");
+  hipError_t e = launch_rprop(p, g, prev, step, n, eta_minus, eta_plus, step_min, step_max,
+                              (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "Rprop launch");
+  return PRISM_OK;
+}
+
+int32_t prism_profile_enable(prism_problem* h, int32_t enable, int32_t max_launches) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  for (auto e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
+  h->ev_used = 0;
+  h->prof = enable != 0;
+  if (!h->prof) return PRISM_OK;
+  if (max_launches < 1) return fail(PRISM_E_INVALID, "max_launches must be >= 1");
+  h->ev.resize((size_t)max_launches * 2);
+  for (auto& e : h->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+  }
+  return PRISM_OK;
+}
+
+int32_t prism_profile_read(prism_problem* h, double* total_ms, int32_t* launches) {
+  if (!h || !total_ms || !launches) return fail(PRISM_E_INVALID, "NULL argument");
+  double tot = 0.0;
+  const int n = h->ev_used / 2;
+  if (n > 0) {
+    hipError_t r = hipEventSynchronize(h->ev[h->ev_used - 1]);
+    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+  }
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.0f;
+    hipError_t r = hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]);
+    if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = n;
+  h->ev_used = 0;
+  return PRISM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal structures shared by the host planner (prism_host.cpp) and the
+// kernels (prism_kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace prism {
+
+constexpr int kBlock = 256;          // threads per block of the fused pass (4 waves)
+constexpr int kWave = 64;
+constexpr int kMaxK = 6;
+constexpr int kMaxC = kMaxK + 3;     // tissue compartments (csf, gm, wm_1..K, res)
+constexpr int kAcqStride = 12;       // floats per staged measurement
+constexpr int kRecHead = 15;         // record fields before alpha[N], beta[N]
+// record field indices (float64)
+enum RecField : int {
+  kRecData = 0,     // data-term partial: MSE sum r^2, NLL sum of the positive parts
+  kRecSpatial = 1,  // Huber-Laplacian partial (written by k_spatial)
+  kRecRep = 2,      // repulsion partial
+  kRecSparse = 3,   // sparsity partial
+  kRecSigma = 4,    // NLL: sum of (r^2/s^2 + 2z(1-R)) (d/dsigma_log = 2N|M| - this)
+  kRecBias = 5,     // 10 slots: sum_x phi_j(x) dlogB(x)
+  kRecAlpha = kRecHead
+};
+
+struct GroupDev {
+  int64_t micro_off;  // float offset of theta_micro / grad_micro
+  int64_t cal_off;    // float offset of theta_cal / grad_cal
+  int64_t y_off;      // float offset of y / yhat
+  int64_t vox_off;    // offset into per-voxel tables (coords)
+  int64_t nbr_off;    // int32 offset of the neighbour table [nbh][V]
+  int64_t w_off;      // float offset of the spatial weights [C][V] in the workspace
+  int64_t glb_off;    // float offset of per-voxel dL/dlogB [V] in the workspace (trilinear)
+  int64_t rec_off;    // float64 offset of the group's first item record
+  int64_t grid_off;   // int32 offset of the dense raster->voxel index grid (trilinear)
+  int32_t V, N, K, C, P;
+  int32_t mode, bias, n_bias, learn_d, nbh, priors;
+  int32_t nx, ny, nz;
+  int32_t acq_off;    // offset of the group's measurements in the acquisition arrays
+  int32_t rec_stride; // float64 fields per record
+  int32_t item_begin, item_count;
+  int32_t tile_begin, tile_count;  // first-stage reduction tiles of this group
+  float invM;         // 1/|M| (0 when the group is empty)
+};
+
+struct ItemDev {
+  int32_t group;
+  int32_t v0;   // first voxel (group-local)
+  int32_t nv;   // voxels
+  int32_t rec;  // record index within the group
+};
+
+// first-stage reduction tile: records [r0, r0+nr) of one group, fields [f0, f0+nf)
+struct TileDev {
+  int32_t group, r0, nr, f0, nf, out;  // out: float64 offset of the tile's partial row
+};
+
+struct ModelDev {
+  float d_csf, d_gm, d_res, d_par, d_perp;
+  float lam_sp, huber_delta, lam_rep, lam_sparse, tau_sparse;
+  float lam_alpha, lam_beta, lam_bias;
+};
+
+struct PassArgs {
+  const GroupDev* groups;
+  const ItemDev* items;
+  const float* bval;
+  const float* bvec;
+  const int32_t* coords;   // packed i | j << 10 | k << 20
+  const int32_t* nbr;
+  const float* y;
+  const float* th_micro;
+  const float* th_cal;
+  float* g_micro;
+  double* rec;
+  float* wsp;              // workspace floats (spatial weights, per-voxel dlogB)
+  uint32_t* status;
+  ModelDev model;
+  int32_t item_base;       // first item of this launch
+  int32_t n_items;         // items in this launch
+  int32_t n_split;         // waves sharing a voxel row
+  int32_t synth_only;      // forward model only (yhat written to g_micro as float [N][V])
+  float* yhat;
+};
+
+struct ReduceArgs {
+  const GroupDev* groups;
+  const TileDev* tiles;
+  const double* rec;
+  double* part;            // first-stage partial rows
+  const float* th_cal;
+  float* g_cal;
+  double* loss;
+  const float* wsp;
+  const int32_t* grid;
+  const int32_t* coords;
+  uint32_t* status;
+  ModelDev model;
+  int32_t n_tiles;
+  int32_t n_groups;
+};
+
+// launchers (prism_kernels.hip)
+hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s);
+hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
+                            hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, int max_tile_fields, hipStream_t s);
+hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups, int n_tri,
+                                 hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, int32_t* step, hipStream_t s);
+hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n,
+                        float em, float ep, float smin, float smax, hipStream_t s);
+
+}  // namespace prism

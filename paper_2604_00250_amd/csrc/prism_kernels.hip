@@ -1,0 +1,997 @@
+// HIP kernels of the PRISM analysis-by-synthesis pass for gfx950 (CDNA4, wave64).
+//
+// k_pass      fused forward (Eq. 3-6) + data term (Eq. 8/9) + adjoint, one
+//             thread block per work item (a contiguous run of one group's
+//             voxels); lane = voxel, loop over measurements with the
+//             acquisition staged in LDS; exps are recomputed, never stored.
+// k_synth     forward model only (yhat).
+// k_spatial   Eq. 7 residual weights rho'(r)/|N| per voxel and compartment.
+// k_reduce1/2 deterministic two-stage reduction of per-item records into the
+//             calibration gradient and the loss terms.
+// k_bias_tri  gradient of the 8^3 trilinear log-bias grid.
+// k_adam, k_rprop  optimiser steps.
+#include "prism_device.h"
+#include "prism_internal.h"
+
+namespace prism {
+
+enum { kMSE = 0, kNLL = 1 };
+enum { kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8 };
+enum { kStNonfiniteLoss = 1, kStNonfiniteGrad = 2, kStZeroDir = 4 };
+
+// ---------------------------------------------------------------------------
+// staging of one measurement: 3 x float4
+//   a = (gx, gy, gz, kpar)   kpar  = -b Dpar log2(e)   (Dpar = 1 with learned D)
+//   b = (kperp, Ecsf, Egm, Eres)                          Eq. 4
+//   c = (exp(alpha_n), beta_n, P2, Q2)  P2 = -2 b Dpar, Q2 = 2 b Dperp
+// ---------------------------------------------------------------------------
+__device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* acq) {
+  const float* cal = A.th_cal + g.cal_off;
+  const float* alpha = cal + g.n_bias;
+  const float* beta = alpha + g.N;
+  const float dpar = g.learn_d ? 1.0f : A.model.d_par;
+  const float dperp = g.learn_d ? 1.0f : A.model.d_perp;
+  for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
+    const float b = A.bval[g.acq_off + n];
+    const float* gv = A.bvec + 3 * (int64_t)(g.acq_off + n);
+    acq[3 * n + 0] = make_float4(gv[0], gv[1], gv[2], -b * dpar * kLog2e);
+    acq[3 * n + 1] = make_float4(-b * dperp * kLog2e, expf(-b * A.model.d_csf),
+                                 expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
+    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b * dpar, 2.0f * b * dperp);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-voxel state
+// ---------------------------------------------------------------------------
+template <int K, bool LD>
+struct Vox {
+  float F[K + 3];   // S0 * fraction, order csf, gm, wm_0..wm_{K-1}, res
+  float d[K][3];    // unit directions
+  float fin, omf;   // f_intra, 1 - f_intra
+  float B;          // bias field
+  float dpar, dperp;
+};
+
+// per-voxel adjoint accumulators as one register array (constant indices only)
+template <int K, bool LD>
+struct Acc {
+  static constexpr int C = K + 3;
+  static constexpr int kGd = C;               // sum_n dc_k g_n      (dL/dd_k), 3K
+  static constexpr int kFin = C + 3 * K;      // sum_n sum_k dE_k e1 (1 - e2)
+  static constexpr int kLogB = C + 3 * K + 1; // sum_n seed (yhat - beta)
+  static constexpr int kDpar = C + 3 * K + 2; // learned diffusivities
+  static constexpr int kDperp = C + 3 * K + 3;
+  static constexpr int N = C + 3 * K + 2 + (LD ? 2 : 0);
+  float r[N];                                 // r[c] = sum_n dS E_c (dL/dF_c)
+};
+
+// raw parameter rows of theta_micro [P][V]
+__device__ __forceinline__ int row_logit(int c) { return 1 + c; }
+__device__ __forceinline__ int row_v(int C, int k, int a) { return C + 1 + 3 * k + a; }
+__device__ __forceinline__ int row_fin(int C, int K) { return C + 1 + 3 * K; }
+__device__ __forceinline__ int row_dpar(int C, int K) { return C + 2 + 3 * K; }
+
+struct Derived {            // quantities the epilogue needs again
+  float S0, sig_s;
+  float f[kMaxC];
+  float invn[kMaxK];
+  float sig_dpar, sig_dperp;
+};
+
+__device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, int32_t pc) {
+  if (g.bias == 0) return 0.0f;
+  const int i = pc & 1023, j = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
+  if (g.bias == 1) {
+    const float x = g.nx > 1 ? (2.0f * i - (g.nx - 1)) / (float)(g.nx - 1) : 0.0f;
+    const float y = g.ny > 1 ? (2.0f * j - (g.ny - 1)) / (float)(g.ny - 1) : 0.0f;
+    const float z = g.nz > 1 ? (2.0f * k - (g.nz - 1)) / (float)(g.nz - 1) : 0.0f;
+    float s = cal[0];
+    s = fmaf(cal[1], x, s);
+    s = fmaf(cal[2], y, s);
+    s = fmaf(cal[3], z, s);
+    s = fmaf(cal[4], x * x, s);
+    s = fmaf(cal[5], y * y, s);
+    s = fmaf(cal[6], z * z, s);
+    s = fmaf(cal[7], x * y, s);
+    s = fmaf(cal[8], x * z, s);
+    s = fmaf(cal[9], y * z, s);
+    return s;
+  }
+  // trilinear 8^3: control point c sits at voxel c (n-1)/7 along each axis
+  float p[3];
+  int i0[3];
+  const int ii[3] = {i, j, k};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float pa = nn[a] > 1 ? ii[a] * (7.0f / (float)(nn[a] - 1)) : 0.0f;
+    int c = (int)floorf(pa);
+    c = c > 6 ? 6 : c;
+    i0[a] = c;
+    p[a] = pa - c;
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const float w = (cx ? p[0] : 1.0f - p[0]) * (cy ? p[1] : 1.0f - p[1]) *
+                        (cz ? p[2] : 1.0f - p[2]);
+        s = fmaf(w, cal[((i0[0] + cx) * 8 + (i0[1] + cy)) * 8 + (i0[2] + cz)], s);
+      }
+  return s;
+}
+
+// Prologue: raw parameters of voxel v -> constrained quantities (Sec. 2.2, 2.5).
+template <int K, bool LD>
+__device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g, int v,
+                                           Vox<K, LD>& x, Derived& dv, bool& zero_dir) {
+  constexpr int C = K + 3;
+  const float* th = A.th_micro + g.micro_off;
+  const int64_t V = g.V;
+  const float s = th[v];
+  dv.S0 = softplus_f(s);
+  dv.sig_s = sigmoid_f(s);
+  float lg[C];
+  float m = -INFINITY;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    lg[c] = th[(int64_t)row_logit(c) * V + v];
+    m = fmaxf(m, lg[c]);
+  }
+  float sum = 0.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    lg[c] = expf(lg[c] - m);
+    sum += lg[c];
+  }
+  const float inv = 1.0f / sum;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    dv.f[c] = lg[c] * inv;
+    x.F[c] = dv.S0 * dv.f[c];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float vx = th[(int64_t)row_v(C, k, 0) * V + v];
+    const float vy = th[(int64_t)row_v(C, k, 1) * V + v];
+    const float vz = th[(int64_t)row_v(C, k, 2) * V + v];
+    const float n2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+    float in = 0.0f;
+    if (n2 > 0.0f) {
+      in = 1.0f / sqrtf(n2);
+    } else {
+      zero_dir = true;
+    }
+    dv.invn[k] = in;
+    x.d[k][0] = vx * in;
+    x.d[k][1] = vy * in;
+    x.d[k][2] = vz * in;
+  }
+  x.fin = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
+  x.omf = 1.0f - x.fin;
+  if (LD) {
+    const float a = th[(int64_t)row_dpar(C, K) * V + v];
+    const float b = th[(int64_t)(row_dpar(C, K) + 1) * V + v];
+    x.dpar = softplus_f(a);
+    x.dperp = softplus_f(b);
+    dv.sig_dpar = sigmoid_f(a);
+    dv.sig_dperp = sigmoid_f(b);
+  } else {
+    x.dpar = 0.0f;
+    x.dperp = 0.0f;
+    dv.sig_dpar = 0.0f;
+    dv.sig_dperp = 0.0f;
+  }
+  const float* cal = A.th_cal + g.cal_off;
+  x.B = expf(log_bias(g, cal, A.coords[g.vox_off + v]));
+}
+
+// ---------------------------------------------------------------------------
+// one (voxel, measurement) pair: forward, data term, adjoint accumulation
+// ---------------------------------------------------------------------------
+template <int K, int MODE, bool LD, bool MASKED>
+__device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv,
+                                     const float4 a, const float4 b, const float4 c, float valid,
+                                     float inv_s2, float& lacc, float& sacc, float& pa, float& pb) {
+  const float gx = a.x, gy = a.y, gz = a.z;
+  float S = x.F[0] * b.y;
+  S = fmaf(x.F[1], b.z, S);
+  S = fmaf(x.F[K + 2], b.w, S);
+  float cc[K], e1[K], e2[K], oe[K], h[K], E[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    cc[k] = fmaf(gz, x.d[k][2], fmaf(gy, x.d[k][1], gx * x.d[k][0]));
+    const float c2 = cc[k] * cc[k];
+    const float kp = LD ? a.w * x.dpar : a.w;
+    const float kq = LD ? b.x * x.dperp : b.x;
+    e1[k] = ex2(kp * c2);                 // exp(-b Dpar cos^2)
+    e2[k] = ex2(fmaf(-kq, c2, kq));       // exp(-b Dperp sin^2)
+    oe[k] = x.omf * e2[k];
+    h[k] = x.fin + oe[k];
+    E[k] = e1[k] * h[k];                  // Eq. 5
+    S = fmaf(x.F[2 + k], E[k], S);        // Eq. 3
+  }
+  const float AB = c.x * x.B;
+  const float q = AB * S;                 // yhat - beta
+  const float yh = q + c.y;               // Eq. 6
+  float seed;
+  if (MODE == kMSE) {
+    float r = yh - yv;
+    if (MASKED) r *= valid;
+    seed = r;
+    lacc = fmaf(r, r, lacc);
+  } else {
+    const float ay = fabsf(yv), ah = fabsf(yh);
+    const float z = ay * ah * inv_s2;
+    float omr;
+    const float li = log_i0e(z, omr);
+    const float dd = ah - ay;
+    float term = fmaf(dd * dd, 0.5f * inv_s2, -li);
+    float sd = fmaf(ay, omr, dd) * inv_s2;
+    float ds = fmaf(dd * dd, inv_s2, 2.0f * z * omr);
+    if (MASKED) {
+      term *= valid;
+      sd *= valid;
+      ds *= valid;
+    }
+    seed = copysignf(sd, yh);
+    lacc += term;
+    sacc += ds;
+  }
+  const float sq = seed * q;
+  pa += sq;
+  pb += seed;
+  acc.r[Acc<K, LD>::kLogB] += sq;
+  const float dS = seed * AB;
+  acc.r[0] = fmaf(dS, b.y, acc.r[0]);
+  acc.r[1] = fmaf(dS, b.z, acc.r[1]);
+  acc.r[K + 2] = fmaf(dS, b.w, acc.r[K + 2]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc.r[2 + k] = fmaf(dS, E[k], acc.r[2 + k]);
+    const float dE = dS * x.F[2 + k];
+    const float e12 = e1[k] * e2[k];
+    acc.r[Acc<K, LD>::kFin] = fmaf(dE, e1[k] - e12, acc.r[Acc<K, LD>::kFin]);
+    const float p2 = LD ? c.z * x.dpar : c.z;
+    const float q2 = LD ? c.w * x.dperp : c.w;
+    // dE/dcos = cos e1 (P2 h + Q2 (1-fin) e2)
+    const float t = fmaf(q2, oe[k], p2 * h[k]);
+    const float dc = dE * (cc[k] * e1[k]) * t;
+    acc.r[Acc<K, LD>::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[Acc<K, LD>::kGd + 3 * k + 0]);
+    acc.r[Acc<K, LD>::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[Acc<K, LD>::kGd + 3 * k + 1]);
+    acc.r[Acc<K, LD>::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[Acc<K, LD>::kGd + 3 * k + 2]);
+    if (LD) {
+      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 e1 (1-fin) e2, with -b = P2/2
+      const float mb = 0.5f * c.z;
+      const float c2 = cc[k] * cc[k];
+      acc.r[Acc<K, LD>::kDpar] = fmaf(dE * E[k], mb * c2, acc.r[Acc<K, LD>::kDpar]);
+      acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe[k], mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
+    }
+  }
+}
+
+constexpr int kLossFlush = 16;  // measurements summed in float32 before a float64 add
+
+// ---------------------------------------------------------------------------
+// fused pass
+// ---------------------------------------------------------------------------
+template <int K, int MODE, bool LD, int VL>
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
+  extern __shared__ float4 smem4[];
+  __shared__ double red[4][16];
+  constexpr int C = K + 3;
+  constexpr int NACC = Acc<K, LD>::N;
+  const ItemDev it = A.items[A.item_base + blockIdx.x];
+  const GroupDev g = A.groups[it.group];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int WN = A.n_split, rows = 4 / WN;
+  const int row = wave / WN, split = wave - row * WN;
+  const int N = g.N;
+  float4* acq = smem4;
+  float* accab = reinterpret_cast<float*>(smem4 + 3 * N);  // [4][2][N]
+  float* xbuf = accab + 8 * N;                               // [rows][WN-1][NACC][64*VL]
+
+  stage_acquisition(A, g, acq);
+  for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
+  __syncthreads();
+
+  const int nb = (N * split) / WN, ne = (N * (split + 1)) / WN;
+  const int64_t V = g.V;
+  const float* yg = A.y + g.y_off;
+  const float* cal = A.th_cal + g.cal_off;
+  const float inv_s2 = MODE == kNLL ? expf(-2.0f * cal[g.n_bias + 2 * N]) : 0.0f;
+  const float sdata = MODE == kMSE ? 2.0f * g.invM : 1.0f;
+  const bool has_sp = (g.priors & kPriorSpatial) && g.nbh > 0;
+  float* wacc = accab + wave * 2 * N;
+
+  double dloss = 0.0, dsig = 0.0, drep = 0.0, dspa = 0.0;
+  float pbias[10];
+#pragma unroll
+  for (int j = 0; j < 10; ++j) pbias[j] = 0.0f;
+  bool bad_grad = false, zero_dir = false;
+
+  const int chunk = 64 * VL * rows;
+  for (int cb = 0; cb < it.nv; cb += chunk) {
+    int vox[VL];
+    float valid[VL];
+#pragma unroll
+    for (int j = 0; j < VL; ++j) {
+      const int lv = cb + row * 64 * VL + j * 64 + lane;
+      const bool ok = lv < it.nv;
+      valid[j] = ok ? 1.0f : 0.0f;
+      vox[j] = it.v0 + (ok ? lv : 0);
+    }
+    const bool full = cb + chunk <= it.nv;
+    Vox<K, LD> x[VL];
+    Derived dv[VL];
+    Acc<K, LD> acc[VL];
+#pragma unroll
+    for (int j = 0; j < VL; ++j) {
+      load_voxel<K, LD>(A, g, vox[j], x[j], dv[j], zero_dir);
+#pragma unroll
+      for (int i = 0; i < NACC; ++i) acc[j].r[i] = 0.0f;
+    }
+
+    // measurement loop with a 2-deep prefetch of y
+    float yb0[VL], yb1[VL];
+#pragma unroll
+    for (int j = 0; j < VL; ++j) {
+      yb0[j] = nb < ne ? yg[(int64_t)nb * V + vox[j]] : 0.0f;
+      yb1[j] = nb + 1 < ne ? yg[(int64_t)(nb + 1) * V + vox[j]] : 0.0f;
+    }
+    for (int n0 = nb; n0 < ne; n0 += kLossFlush) {
+      const int n1 = min(n0 + kLossFlush, ne);
+      float lacc = 0.0f, sacc = 0.0f;
+      for (int n = n0; n < n1; ++n) {
+        float ycur[VL];
+#pragma unroll
+        for (int j = 0; j < VL; ++j) {
+          ycur[j] = yb0[j];
+          yb0[j] = yb1[j];
+          yb1[j] = n + 2 < ne ? yg[(int64_t)(n + 2) * V + vox[j]] : 0.0f;
+        }
+        const float4 a = acq[3 * n + 0];
+        const float4 b = acq[3 * n + 1];
+        const float4 c = acq[3 * n + 2];
+        float pa = 0.0f, pb = 0.0f;
+        if (full) {
+#pragma unroll
+          for (int j = 0; j < VL; ++j)
+            pair<K, MODE, LD, false>(x[j], acc[j], ycur[j], a, b, c, 1.0f, inv_s2, lacc, sacc, pa,
+                                     pb);
+        } else {
+#pragma unroll
+          for (int j = 0; j < VL; ++j)
+            pair<K, MODE, LD, true>(x[j], acc[j], ycur[j], a, b, c, valid[j], inv_s2, lacc, sacc,
+                                    pa, pb);
+        }
+        // per-measurement sums over the wave's voxels (alpha_n, beta_n adjoints)
+        pa = wave_sum_to_63(pa);
+        pb = wave_sum_to_63(pb);
+        if (lane == 63) {
+          wacc[n] += pa;
+          wacc[N + n] += pb;
+        }
+      }
+      dloss += (double)lacc;
+      dsig += (double)sacc;
+    }
+
+    // combine the per-voxel accumulators of the waves that split this row over n
+    if (WN > 1) {
+      if (split > 0) {
+#pragma unroll
+        for (int j = 0; j < VL; ++j) {
+          float* dst = xbuf + (((row * (WN - 1) + split - 1) * NACC) * 64 * VL) + j * 64 + lane;
+#pragma unroll
+          for (int i = 0; i < NACC; ++i) dst[i * 64 * VL] = acc[j].r[i];
+        }
+      }
+      __syncthreads();
+      if (split == 0) {
+        for (int s = 1; s < WN; ++s) {
+#pragma unroll
+          for (int j = 0; j < VL; ++j) {
+            const float* src = xbuf + (((row * (WN - 1) + s - 1) * NACC) * 64 * VL) + j * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < NACC; ++i) acc[j].r[i] += src[i * 64 * VL];
+          }
+        }
+      }
+    }
+
+    // epilogue: priors, chain rule to raw parameters, gradient store
+    if (split == 0) {
+      float* gm = A.g_micro + g.micro_off;
+      const float sc_rep = A.model.lam_rep * g.invM;
+      const float sc_spa = A.model.lam_sparse * g.invM;
+      const float sc_sp = A.model.lam_sp * g.invM;
+#pragma unroll
+      for (int j = 0; j < VL; ++j) {
+        if (valid[j] == 0.0f) continue;
+        const int v = vox[j];
+        const Derived& D = dv[j];
+        float gF[C], gf[C];
+        float gS0 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          gF[c] = sdata * acc[j].r[c];
+          gf[c] = D.S0 * gF[c];
+          gS0 = fmaf(D.f[c], gF[c], gS0);
+        }
+        float gd[K][3];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) gd[k][a] = sdata * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
+        if (has_sp) {
+          const float* w = A.wsp + g.w_off;
+          const int32_t* nbr = A.nbr + g.nbr_off;
+          float sum[C];
+#pragma unroll
+          for (int c = 0; c < C; ++c) sum[c] = 0.0f;
+          int cnt = 0;
+          for (int q = 0; q < g.nbh; ++q) {
+            const int u = nbr[(int64_t)q * V + v];
+            if (u >= 0) {
+              ++cnt;
+#pragma unroll
+              for (int c = 0; c < C; ++c) sum[c] += w[(int64_t)c * V + u];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < C; ++c)
+            gf[c] = fmaf(sc_sp, fmaf(w[(int64_t)c * V + v], (float)cnt, -sum[c]), gf[c]);
+        }
+        if (g.priors & kPriorRep) {
+          float lr = 0.0f;
+#pragma unroll
+          for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int k = i + 1; k < K; ++k) {
+              const float dot = x[j].d[i][0] * x[j].d[k][0] + x[j].d[i][1] * x[j].d[k][1] +
+                                x[j].d[i][2] * x[j].d[k][2];
+              const float ad = fabsf(dot);
+              const float sg = dot > 0.0f ? 1.0f : (dot < 0.0f ? -1.0f : 0.0f);
+              const float fi = D.f[2 + i], fk = D.f[2 + k];
+              lr = fmaf(fi * fk, ad, lr);
+              gf[2 + i] = fmaf(sc_rep * fk, ad, gf[2 + i]);
+              gf[2 + k] = fmaf(sc_rep * fi, ad, gf[2 + k]);
+              const float w2 = sc_rep * fi * fk * sg;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                gd[i][a] = fmaf(w2, x[j].d[k][a], gd[i][a]);
+                gd[k][a] = fmaf(w2, x[j].d[i][a], gd[k][a]);
+              }
+            }
+          drep += (double)lr;
+        }
+        if (g.priors & kPriorSparse) {
+          float ls = 0.0f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float fk = D.f[2 + k];
+            if (fk < A.model.tau_sparse) {
+              ls += fk;
+              gf[2 + k] += sc_spa;
+            }
+          }
+          dspa += (double)ls;
+        }
+        // softmax chain rule
+        float gsum = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) gsum = fmaf(D.f[c], gf[c], gsum);
+        float gout[4 * kMaxK + 7];
+        gout[0] = D.sig_s * gS0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) gout[row_logit(c)] = D.f[c] * (gf[c] - gsum);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float pr = gd[k][0] * x[j].d[k][0] + gd[k][1] * x[j].d[k][1] + gd[k][2] * x[j].d[k][2];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            gout[row_v(C, k, a)] = (gd[k][a] - pr * x[j].d[k][a]) * D.invn[k];
+        }
+        gout[row_fin(C, K)] = x[j].fin * x[j].omf * sdata * acc[j].r[Acc<K, LD>::kFin];
+        if (LD) {
+          gout[row_dpar(C, K)] = D.sig_dpar * sdata * acc[j].r[Acc<K, LD>::kDpar];
+          gout[row_dpar(C, K) + 1] = D.sig_dperp * sdata * acc[j].r[Acc<K, LD>::kDperp];
+        }
+        constexpr int P = 4 * K + 5 + (LD ? 2 : 0);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          if (!isfinite(gout[p])) bad_grad = true;
+          gm[(int64_t)p * V + v] = gout[p];
+        }
+        // bias-field adjoint dL/dlogB(x)
+        const float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
+        if (g.bias == 1) {
+          const int32_t pc = A.coords[g.vox_off + v];
+          const int i = pc & 1023, jj = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
+          const float xx = g.nx > 1 ? (2.0f * i - (g.nx - 1)) / (float)(g.nx - 1) : 0.0f;
+          const float yy = g.ny > 1 ? (2.0f * jj - (g.ny - 1)) / (float)(g.ny - 1) : 0.0f;
+          const float zz = g.nz > 1 ? (2.0f * k - (g.nz - 1)) / (float)(g.nz - 1) : 0.0f;
+          const float phi[10] = {1.0f, xx, yy, zz, xx * xx, yy * yy, zz * zz, xx * yy, xx * zz, yy * zz};
+#pragma unroll
+          for (int q = 0; q < 10; ++q) pbias[q] = fmaf(phi[q], glb, pbias[q]);
+        } else if (g.bias == 2) {
+          A.wsp[g.glb_off + v] = glb;
+        }
+      }
+    }
+    if (WN > 1) __syncthreads();  // xbuf is reused by the next chunk
+  }
+
+  // ---- item record: per-problem sums and per-measurement sums ----
+  double* rec = A.rec + g.rec_off + (int64_t)it.rec * g.rec_stride;
+  double vals[14];
+  vals[0] = dloss;
+  vals[1] = drep;
+  vals[2] = dspa;
+  vals[3] = dsig;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) vals[4 + q] = (double)pbias[q];
+#pragma unroll
+  for (int q = 0; q < 14; ++q) {
+    const double s = wave_sum_f64(vals[q]);
+    if (lane == 0) red[wave][q] = s;
+  }
+  if (bad_grad) atomicOr(A.status, (uint32_t)kStNonfiniteGrad);
+  if (zero_dir) atomicOr(A.status, (uint32_t)kStZeroDir);
+  __syncthreads();
+  if (tid < 14) {
+    const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    const int field = tid == 0 ? kRecData : tid == 1 ? kRecRep : tid == 2 ? kRecSparse
+                      : tid == 3 ? kRecSigma : kRecBias + (tid - 4);
+    rec[field] = s;
+  }
+  for (int n = tid; n < N; n += kBlock) {
+    rec[kRecAlpha + n] = (double)accab[n] + (double)accab[2 * N + n] + (double)accab[4 * N + n] +
+                         (double)accab[6 * N + n];
+    rec[kRecAlpha + N + n] = (double)accab[N + n] + (double)accab[3 * N + n] +
+                             (double)accab[5 * N + n] + (double)accab[7 * N + n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward model only
+// ---------------------------------------------------------------------------
+template <int K, bool LD>
+__global__ __launch_bounds__(kBlock) void k_synth(PassArgs A) {
+  extern __shared__ float4 smem4[];
+  const ItemDev it = A.items[A.item_base + blockIdx.x];
+  const GroupDev g = A.groups[it.group];
+  float4* acq = smem4;
+  stage_acquisition(A, g, acq);
+  __syncthreads();
+  const int64_t V = g.V;
+  float* out = A.yhat + g.y_off;
+  bool zero_dir = false;
+  for (int lv = threadIdx.x; lv < it.nv; lv += kBlock) {
+    const int v = it.v0 + lv;
+    Vox<K, LD> x;
+    Derived dv;
+    load_voxel<K, LD>(A, g, v, x, dv, zero_dir);
+    for (int n = 0; n < g.N; ++n) {
+      const float4 a = acq[3 * n], b = acq[3 * n + 1], c = acq[3 * n + 2];
+      float S = x.F[0] * b.y;
+      S = fmaf(x.F[1], b.z, S);
+      S = fmaf(x.F[K + 2], b.w, S);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float cc = fmaf(a.z, x.d[k][2], fmaf(a.y, x.d[k][1], a.x * x.d[k][0]));
+        const float c2 = cc * cc;
+        const float kp = LD ? a.w * x.dpar : a.w;
+        const float kq = LD ? b.x * x.dperp : b.x;
+        const float E = ex2(kp * c2) * (x.fin + x.omf * ex2(fmaf(-kq, c2, kq)));
+        S = fmaf(x.F[2 + k], E, S);
+      }
+      out[(int64_t)n * V + v] = fmaf(c.x * x.B, S, c.y);
+    }
+  }
+  if (zero_dir && A.status) atomicOr(A.status, (uint32_t)kStZeroDir);
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 7 residual weights: w_c(x) = rho'(r_c(x)) / |N(x)|, r = f(x) - mean_N f
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, int v, float* f) {
+  float m = -INFINITY;
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c)
+    if (c < C) {
+      f[c] = th[(int64_t)(1 + c) * V + v];
+      m = fmaxf(m, f[c]);
+    }
+  float s = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c)
+    if (c < C) {
+      f[c] = expf(f[c] - m);
+      s += f[c];
+    }
+  const float inv = 1.0f / s;
+#pragma unroll
+  for (int c = 0; c < kMaxC; ++c)
+    if (c < C) f[c] *= inv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
+  __shared__ double red[4];
+  const ItemDev it = A.items[blockIdx.x];
+  const GroupDev g = A.groups[it.group];
+  const int tid = threadIdx.x;
+  double lsum = 0.0;
+  if ((g.priors & kPriorSpatial) && g.nbh > 0) {
+    const float* th = A.th_micro + g.micro_off;
+    const int32_t* nbr = A.nbr + g.nbr_off;
+    const int64_t V = g.V;
+    const int C = g.C;
+    const float delta = A.model.huber_delta;
+    for (int lv = tid; lv < it.nv; lv += kBlock) {
+      const int v = it.v0 + lv;
+      float f[kMaxC], mean[kMaxC], t[kMaxC];
+      softmax_at(th, V, C, v, f);
+#pragma unroll
+      for (int c = 0; c < kMaxC; ++c) mean[c] = 0.0f;
+      int cnt = 0;
+      for (int q = 0; q < g.nbh; ++q) {
+        const int u = nbr[(int64_t)q * V + v];
+        if (u >= 0) {
+          ++cnt;
+          softmax_at(th, V, C, u, t);
+#pragma unroll
+          for (int c = 0; c < kMaxC; ++c)
+            if (c < C) mean[c] += t[c];
+        }
+      }
+      float ls = 0.0f;
+      const float icnt = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
+#pragma unroll
+      for (int c = 0; c < kMaxC; ++c)
+        if (c < C) {
+          float w = 0.0f;
+          if (cnt > 0) {
+            const float r = f[c] - mean[c] * icnt;
+            const float ar = fabsf(r);
+            ls += ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta);
+            w = (ar <= delta ? r : copysignf(delta, r)) * icnt;
+          }
+          A.wsp[g.w_off + (int64_t)c * V + v] = w;
+        }
+      lsum += (double)ls;
+    }
+  }
+  lsum = wave_sum_f64(lsum);
+  if ((tid & 63) == 0) red[tid >> 6] = lsum;
+  __syncthreads();
+  if (tid == 0)
+    A.rec[g.rec_off + (int64_t)it.rec * g.rec_stride + kRecSpatial] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// deterministic two-stage reduction of the item records
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce1(ReduceArgs R) {
+  __shared__ double part[4][64];
+  const TileDev t = R.tiles[blockIdx.x];
+  const GroupDev g = R.groups[t.group];
+  const int f = threadIdx.x & 63, s = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (f < t.nf) {
+    const double* base = R.rec + g.rec_off + t.f0 + f;
+    for (int r = t.r0 + s; r < t.r0 + t.nr; r += 4) acc += base[(int64_t)r * g.rec_stride];
+  }
+  part[s][f] = acc;
+  __syncthreads();
+  if (s == 0) R.part[(int64_t)t.out + f] = part[0][f] + part[1][f] + part[2][f] + part[3][f];
+}
+
+__global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
+  __shared__ double part[4][64];
+  __shared__ double calsq[3][4];
+  const int gi = blockIdx.y, fc = blockIdx.x;
+  const GroupDev g = R.groups[gi];
+  const int nf_total = g.rec_stride;
+  const int nfc = (nf_total + 63) / 64;
+  if (fc >= nfc) return;
+  const int f = threadIdx.x & 63, s = threadIdx.x >> 6;
+  const int nrr = g.item_count > 0 ? (g.item_count + 63) / 64 : 0;
+  double acc = 0.0;
+  for (int rr = s; rr < nrr; rr += 4) acc += R.part[(int64_t)(g.tile_begin + fc * nrr + rr) * 64 + f];
+  part[s][f] = acc;
+  const float* cal = R.th_cal + g.cal_off;
+  float* gc = R.g_cal + g.cal_off;
+  const int N = g.N, nb = g.n_bias;
+  const bool cal_on = (g.priors & kPriorCal) != 0;
+  // calibration L2 (Sec. 2.4) on block 0 of the group
+  if (fc == 0) {
+    double sa = 0.0, sb = 0.0, sw = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) sw += (double)cal[i] * cal[i];
+    for (int i = threadIdx.x; i < N; i += 256) {
+      sa += (double)cal[nb + i] * cal[nb + i];
+      sb += (double)cal[nb + N + i] * cal[nb + N + i];
+    }
+    sa = wave_sum_f64(sa);
+    sb = wave_sum_f64(sb);
+    sw = wave_sum_f64(sw);
+    if ((threadIdx.x & 63) == 0) {
+      calsq[0][s] = sa;
+      calsq[1][s] = sb;
+      calsq[2][s] = sw;
+    }
+  }
+  __syncthreads();
+  if (s != 0) return;
+  const int field = fc * 64 + f;
+  if (field >= nf_total) return;
+  const double tot = part[0][f] + part[1][f] + part[2][f] + part[3][f];
+  const double M = g.V;
+  const double sdata = g.mode == kMSE ? 2.0 * (double)g.invM : 1.0;
+  float out = 0.0f;
+  bool write = false;
+  int dst = -1;
+  if (field == kRecSigma) {
+    dst = nb + 2 * N;
+    out = g.mode == kNLL ? (float)(2.0 * N * M - tot) : 0.0f;
+    write = true;
+  } else if (field >= kRecBias && field < kRecBias + 10) {
+    const int j = field - kRecBias;
+    if (g.bias == 1) {
+      dst = j;
+      out = (float)(tot + (cal_on ? 2.0 * (double)R.model.lam_bias * cal[j] : 0.0));
+      write = true;
+    }
+  } else if (field >= kRecAlpha && field < kRecAlpha + N) {
+    const int n = field - kRecAlpha;
+    dst = nb + n;
+    out = (float)(sdata * tot + (cal_on ? 2.0 * (double)R.model.lam_alpha * cal[nb + n] : 0.0));
+    write = true;
+  } else if (field >= kRecAlpha + N && field < kRecAlpha + 2 * N) {
+    const int n = field - kRecAlpha - N;
+    dst = nb + N + n;
+    out = (float)(sdata * tot + (cal_on ? 2.0 * (double)R.model.lam_beta * cal[nb + N + n] : 0.0));
+    write = true;
+  }
+  if (write) {
+    gc[dst] = out;
+    if (!isfinite(out)) atomicOr(R.status, (uint32_t)kStNonfiniteGrad);
+  }
+  if (fc == 0 && f == 0) {
+    // loss terms from fields 0-4 of the LDS partials of this (first) field chunk
+    auto part_sum = [&](int fld) { return part[0][fld] + part[1][fld] + part[2][fld] + part[3][fld]; };
+    const double data = g.mode == kMSE
+                            ? part_sum(kRecData) * (double)g.invM
+                            : part_sum(kRecData) +
+                                  2.0 * (double)cal[nb + 2 * N] * (double)N * M;
+    const double sp = part_sum(kRecSpatial) * (double)R.model.lam_sp * g.invM;
+    const double rp = part_sum(kRecRep) * (double)R.model.lam_rep * g.invM;
+    const double sa = part_sum(kRecSparse) * (double)R.model.lam_sparse * g.invM;
+    double cl = 0.0;
+    if (cal_on) {
+      const double qa = calsq[0][0] + calsq[0][1] + calsq[0][2] + calsq[0][3];
+      const double qb = calsq[1][0] + calsq[1][1] + calsq[1][2] + calsq[1][3];
+      const double qw = calsq[2][0] + calsq[2][1] + calsq[2][2] + calsq[2][3];
+      cl = (double)R.model.lam_alpha * qa + (double)R.model.lam_beta * qb +
+           (double)R.model.lam_bias * qw;
+    }
+    double* L = R.loss + (int64_t)gi * 6;
+    L[0] = data;
+    L[1] = sp;
+    L[2] = rp;
+    L[3] = sa;
+    L[4] = cl;
+    L[5] = data + sp + rp + sa + cl;
+    if (!isfinite(L[5])) atomicOr(R.status, (uint32_t)kStNonfiniteLoss);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// trilinear 8^3 log-bias gradient: dL/db(c) = sum_x w_c(x) dL/dlogB(x)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* tri_groups) {
+  __shared__ double red[4];
+  const GroupDev g = R.groups[tri_groups[blockIdx.y]];
+  const int cp = blockIdx.x;
+  const int cidx[3] = {cp >> 6, (cp >> 3) & 7, cp & 7};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (nn[a] == 1) {
+      lo[a] = 0;
+      hi[a] = cidx[a] == 0 ? 0 : -1;
+    } else {
+      const float sc = (float)(nn[a] - 1) / 7.0f;
+      lo[a] = max(0, (int)ceilf((cidx[a] - 1) * sc));
+      hi[a] = min(nn[a] - 1, (int)floorf((cidx[a] + 1) * sc));
+    }
+  }
+  double acc = 0.0;
+  const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+  if (ex > 0 && ey > 0 && ez > 0) {
+    const int64_t tot = (int64_t)ex * ey * ez;
+    const int32_t* grid = R.grid + g.grid_off;
+    const float* glb = R.wsp + g.glb_off;
+    for (int64_t q = threadIdx.x; q < tot; q += 256) {
+      const int i = lo[0] + (int)(q / ((int64_t)ey * ez));
+      const int j = lo[1] + (int)((q / ez) % ey);
+      const int k = lo[2] + (int)(q % ez);
+      const int v = grid[((int64_t)i * g.ny + j) * g.nz + k];
+      if (v < 0) continue;
+      const int ii[3] = {i, j, k};
+      float w = 1.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float p = nn[a] > 1 ? ii[a] * (7.0f / (float)(nn[a] - 1)) : 0.0f;
+        w *= fmaxf(0.0f, 1.0f - fabsf(p - (float)cidx[a]));
+      }
+      acc += (double)w * (double)glb[v];
+    }
+  }
+  acc = wave_sum_f64(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double s = red[0] + red[1] + red[2] + red[3];
+    const float* cal = R.th_cal + g.cal_off;
+    const bool cal_on = (g.priors & kPriorCal) != 0;
+    const float out = (float)(s + (cal_on ? 2.0 * (double)R.model.lam_bias * cal[cp] : 0.0));
+    R.g_cal[g.cal_off + cp] = out;
+    if (!isfinite(out)) atomicOr(R.status, (uint32_t)kStNonfiniteGrad);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// optimisers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              int32_t* step) {
+  __shared__ float sc[2];
+  __shared__ int tcur;
+  if (threadIdx.x == 0) {
+    const int t = step[0] + 1;
+    tcur = t;
+    const double bc1 = 1.0 - pow((double)b1, (double)t);
+    const double bc2 = 1.0 - pow((double)b2, (double)t);
+    sc[0] = (float)((double)lr / bc1);
+    sc[1] = (float)(1.0 / sqrt(bc2));
+  }
+  __syncthreads();
+  const float step_size = sc[0], ibc2 = sc[1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float gi = g[i];
+    float mi = m[i], vi = v[i];
+    mi = fmaf(1.0f - b1, gi - mi, mi);
+    vi = fmaf(1.0f - b2, gi * gi, vi * b2);
+    const float denom = fmaf(sqrtf(vi), ibc2, eps);
+    p[i] = p[i] - step_size * (mi / denom);
+    m[i] = mi;
+    v[i] = vi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(&step[1], 1);
+    if (prev == (int)gridDim.x - 1) {
+      atomicExch(&step[0], tcur);
+      atomicExch(&step[1], 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rprop(float* p, const float* g, float* prev, float* st,
+                                               int64_t n, float em, float ep, float smin,
+                                               float smax) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float gi = g[i];
+    const float pr = gi * prev[i];
+    float s = st[i];
+    if (pr > 0.0f) s *= ep;
+    else if (pr < 0.0f) s *= em;
+    s = fminf(fmaxf(s, smin), smax);
+    if (pr < 0.0f) gi = 0.0f;
+    const float sg = gi > 0.0f ? 1.0f : (gi < 0.0f ? -1.0f : 0.0f);
+    p[i] = p[i] - sg * s;
+    prev[i] = gi;
+    st[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static size_t pass_lds_bytes(int maxN, int n_split, int nacc_, int vpl) {
+  const int rows = 4 / n_split;
+  size_t b = (size_t)maxN * 3 * sizeof(float4) + (size_t)8 * maxN * sizeof(float);
+  b += (size_t)rows * (n_split - 1) * nacc_ * 64 * vpl * sizeof(float);
+  return b;
+}
+
+template <int K, int MODE, bool LD, int VL>
+static hipError_t launch_pass_t(const PassArgs& a, hipStream_t s, int maxN) {
+  const size_t lds = pass_lds_bytes(maxN, a.n_split, (K + 3) + 3 * K + 2 + (LD ? 2 : 0), VL);
+  if (a.synth_only) {
+    hipLaunchKernelGGL((k_synth<K, LD>), dim3(a.n_items), dim3(kBlock),
+                       (size_t)maxN * 3 * sizeof(float4), s, a);
+  } else {
+    hipLaunchKernelGGL((k_pass<K, MODE, LD, VL>), dim3(a.n_items), dim3(kBlock), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t dispatch_mode(const PassArgs& a, int mode, int ld, int vpl, hipStream_t s,
+                                int maxN) {
+  if (vpl == 2) {
+    if (mode == kMSE) return ld ? launch_pass_t<K, kMSE, true, 2>(a, s, maxN) : launch_pass_t<K, kMSE, false, 2>(a, s, maxN);
+    return ld ? launch_pass_t<K, kNLL, true, 2>(a, s, maxN) : launch_pass_t<K, kNLL, false, 2>(a, s, maxN);
+  }
+  if (mode == kMSE) return ld ? launch_pass_t<K, kMSE, true, 1>(a, s, maxN) : launch_pass_t<K, kMSE, false, 1>(a, s, maxN);
+  return ld ? launch_pass_t<K, kNLL, true, 1>(a, s, maxN) : launch_pass_t<K, kNLL, false, 1>(a, s, maxN);
+}
+
+hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
+                            hipStream_t s) {
+  switch (K) {
+    case 1: return dispatch_mode<1>(a, mode, learn_d, vpl, s, maxN);
+    case 2: return dispatch_mode<2>(a, mode, learn_d, vpl, s, maxN);
+    case 3: return dispatch_mode<3>(a, mode, learn_d, vpl, s, maxN);
+    case 4: return dispatch_mode<4>(a, mode, learn_d, vpl, s, maxN);
+    case 5: return dispatch_mode<5>(a, mode, learn_d, vpl, s, maxN);
+    case 6: return dispatch_mode<6>(a, mode, learn_d, vpl, s, maxN);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spatial, dim3(n_items), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, int max_field_chunks, hipStream_t s) {
+  if (a.n_tiles > 0) hipLaunchKernelGGL(k_reduce1, dim3(a.n_tiles), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.n_groups > 0 && max_field_chunks > 0)
+    hipLaunchKernelGGL(k_reduce2, dim3(max_field_chunks, a.n_groups), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups, int n_tri,
+                                 hipStream_t s) {
+  if (n_tri <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bias_tri, dim3(512, n_tri), dim3(256), 0, s, a, tri_groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, int32_t* step, hipStream_t s) {
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
+                     eps, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n, float em,
+                        float ep, float smin, float smax, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 1023) / 1024;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rprop, dim3((unsigned)blocks), dim3(256), 0, s, p, g, prev, step, n, em, ep,
+                     smin, smax);
+  return hipGetLastError();
+}
+
+}  // namespace prism

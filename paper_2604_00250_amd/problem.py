@@ -1,0 +1,274 @@
+"""Problem handle and device buffers over the libprism C ABI.
+
+`Problem` wraps a `prism_problem` handle built from `inputs.Group`
+descriptions; `pack_*` / `unpack_*` convert between per-group parameter
+dictionaries and the library's flat layouts (documented in include/prism.h);
+`DeviceState` keeps y, parameters, gradients, optimiser moments, workspace,
+loss and status resident on the GPU (torch tensors, used only as device
+memory) and drives the per-iteration calls on a torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+MICRO_ROWS = ("s0", "logits", "v", "fin", "dpar", "dperp")
+
+
+def n_params_vox(K: int, learn_d: bool) -> int:
+    return 4 * K + 5 + (2 if learn_d else 0)
+
+
+class Problem:
+    """A set of independent groups (each one calibration group of PRISM)."""
+
+    def __init__(self, groups: Sequence, model: Optional[L.Model] = None, launch: Optional[dict] = None):
+        lib = L.lib()
+        self.groups = list(groups)
+        acq_index = {}
+        acqs = []
+        self._keep = []
+        for g in self.groups:
+            key = id(g.acq)
+            if key not in acq_index:
+                acq_index[key] = len(acqs)
+                bval = np.ascontiguousarray(g.acq.bval, dtype=np.float32)
+                bvec = np.ascontiguousarray(g.acq.bvec, dtype=np.float32)
+                self._keep += [bval, bvec]
+                acqs.append(L.Acq(bval.shape[0], bval.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  bvec.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        descs = (L.GroupDesc * len(self.groups))()
+        for i, g in enumerate(self.groups):
+            mask = np.ascontiguousarray(g.mask, dtype=np.uint8)
+            self._keep.append(mask)
+            pri = 0
+            for p in g.priors:
+                pri |= L.PRIOR_BITS[p]
+            nx, ny, nz = g.shape
+            descs[i] = L.GroupDesc(nx, ny, nz, g.K, L.RICIAN if g.mode == "nll" else L.MSE,
+                                   L.BIAS[g.bias], acq_index[id(g.acq)], int(g.neighbourhood),
+                                   int(bool(g.learn_diffusivity)), pri,
+                                   mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        acq_arr = (L.Acq * len(acqs))(*acqs)
+        self.model = model if model is not None else L.model_defaults()
+        h = ctypes.c_void_p()
+        L.check(lib.prism_problem_create(ctypes.byref(h), descs, len(self.groups), acq_arr,
+                                         len(acqs), ctypes.byref(self.model)))
+        self.handle = h
+        self._keep = None
+        info = L.ProblemInfo()
+        L.check(lib.prism_problem_info(h, ctypes.byref(info)))
+        self.info = info
+        self.ginfo = []
+        for i in range(len(self.groups)):
+            gi = L.GroupInfo()
+            L.check(lib.prism_group_info(h, i, ctypes.byref(gi)))
+            self.ginfo.append(gi)
+        if launch:
+            self.tune(**launch)
+
+    # -- handle management -------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().prism_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tune(self, vox_per_lane=1, n_split=1, item_vox=0):
+        L.check(L.lib().prism_problem_tune(self.handle, ctypes.byref(L.Launch(vox_per_lane, n_split, item_vox, 0))))
+
+    def launch(self) -> dict:
+        ln = L.Launch()
+        L.check(L.lib().prism_problem_launch(self.handle, ctypes.byref(ln)))
+        return dict(vox_per_lane=ln.vox_per_lane, n_split=ln.n_split, item_vox=ln.item_vox)
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        L.check(L.lib().prism_workspace_bytes(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    @property
+    def n_groups(self):
+        return len(self.groups)
+
+    # -- host-side layout conversion ----------------------------------------
+    def pack_micro(self, thetas: Sequence[dict]) -> np.ndarray:
+        out = np.zeros(self.info.n_micro, dtype=np.float32)
+        for g, gi, th in zip(self.groups, self.ginfo, thetas):
+            V = int(gi.n_vox)
+            rows = [np.asarray(th["s0"]).reshape(1, V), np.asarray(th["logits"]).reshape(-1, V),
+                    np.asarray(th["v"]).reshape(-1, V), np.asarray(th["fin"]).reshape(1, V)]
+            if g.learn_diffusivity:
+                rows += [np.asarray(th["dpar"]).reshape(1, V), np.asarray(th["dperp"]).reshape(1, V)]
+            blk = np.concatenate(rows, 0).astype(np.float32)
+            assert blk.shape[0] == gi.n_params_vox
+            out[gi.micro_offset:gi.micro_offset + blk.size] = blk.reshape(-1)
+        return out
+
+    def pack_cal(self, thetas: Sequence[dict]) -> np.ndarray:
+        out = np.zeros(self.info.n_cal, dtype=np.float32)
+        for gi, th in zip(self.ginfo, thetas):
+            vec = np.concatenate([np.asarray(th["bias"], dtype=np.float32).reshape(-1),
+                                  np.asarray(th["alpha"], dtype=np.float32).reshape(-1),
+                                  np.asarray(th["beta"], dtype=np.float32).reshape(-1),
+                                  np.asarray(th["sigma_log"], dtype=np.float32).reshape(1)])
+            assert vec.size == gi.n_cal, (vec.size, gi.n_cal)
+            out[gi.cal_offset:gi.cal_offset + vec.size] = vec
+        return out
+
+    def pack_y(self, ys: Sequence[np.ndarray]) -> np.ndarray:
+        out = np.empty(self.info.n_y, dtype=np.float32)
+        for gi, y in zip(self.ginfo, ys):
+            out[gi.y_offset:gi.y_offset + y.size] = np.asarray(y, dtype=np.float32).reshape(-1)
+        return out
+
+    def unpack_micro(self, flat: np.ndarray) -> list:
+        res = []
+        for g, gi in zip(self.groups, self.ginfo):
+            V, K = int(gi.n_vox), g.K
+            blk = np.asarray(flat[gi.micro_offset:gi.micro_offset + gi.n_params_vox * V]).reshape(-1, V)
+            C = K + 3
+            d = dict(s0=blk[0], logits=blk[1:1 + C], v=blk[1 + C:1 + C + 3 * K].reshape(K, 3, V),
+                     fin=blk[1 + C + 3 * K])
+            if g.learn_diffusivity:
+                d["dpar"] = blk[2 + C + 3 * K]
+                d["dperp"] = blk[3 + C + 3 * K]
+            res.append(d)
+        return res
+
+    def unpack_cal(self, flat: np.ndarray) -> list:
+        res = []
+        for gi in self.ginfo:
+            vec = np.asarray(flat[gi.cal_offset:gi.cal_offset + gi.n_cal])
+            nb, N = gi.n_bias, gi.n_meas
+            res.append(dict(bias=vec[:nb], alpha=vec[nb:nb + N], beta=vec[nb + N:nb + 2 * N],
+                            sigma_log=vec[nb + 2 * N]))
+        return res
+
+    def unpack_y(self, flat: np.ndarray) -> list:
+        return [np.asarray(flat[gi.y_offset:gi.y_offset + gi.n_meas * gi.n_vox]).reshape(gi.n_meas, int(gi.n_vox))
+                for gi in self.ginfo]
+
+    # -- raw calls on device pointers ----------------------------------------
+    def loss_grad_ptr(self, y, th_micro, th_cal, loss, g_micro, g_cal, ws, ws_bytes, status, stream):
+        L.check(L.lib().prism_loss_grad(self.handle, y, th_micro, th_cal, loss, g_micro, g_cal, ws,
+                                        ws_bytes, status, stream))
+
+    def synthesize_ptr(self, th_micro, th_cal, yhat, stream):
+        L.check(L.lib().prism_synthesize(self.handle, th_micro, th_cal, yhat, stream))
+
+    def profile(self, enable: bool, max_launches: int = 4096):
+        L.check(L.lib().prism_profile_enable(self.handle, int(enable), int(max_launches)))
+
+    def profile_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        L.check(L.lib().prism_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+
+def adam_step_ptr(p, g, m, v, n, lr, beta1, beta2, eps, step, stream):
+    L.check(L.lib().prism_adam_step(p, g, m, v, int(n), float(lr), float(beta1), float(beta2),
+                                    float(eps), step, stream))
+
+
+def rprop_step_ptr(p, g, prev, step, n, eta_minus, eta_plus, step_min, step_max, stream):
+    L.check(L.lib().prism_rprop_step(p, g, prev, step, int(n), float(eta_minus), float(eta_plus),
+                                     float(step_min), float(step_max), stream))
+
+
+class DeviceState:
+    """Everything one fit needs, resident in HBM.
+
+    The parameters live in ONE flat buffer `params` = [theta_micro | theta_cal]
+    (and the gradient likewise), so one optimiser call updates both.
+    """
+
+    def __init__(self, prob: Problem, ys=None, thetas=None, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.device = torch.device(device)
+        info = prob.info
+        self.n_micro, self.n_cal, self.n_y = int(info.n_micro), int(info.n_cal), int(info.n_y)
+        n = self.n_micro + self.n_cal
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.params = torch.zeros(n, **f32)
+        self.grad = torch.zeros(n, **f32)
+        self.m = torch.zeros(n, **f32)
+        self.v = torch.zeros(n, **f32)
+        self.y = torch.zeros(max(self.n_y, 1), **f32)
+        self.loss = torch.zeros((prob.n_groups, 6), dtype=torch.float64, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.step = torch.zeros(2, dtype=torch.int32, device=self.device)
+        self.ws_bytes = prob.workspace_bytes()
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        if ys is not None:
+            self.set_y(ys)
+        if thetas is not None:
+            self.set_params(thetas)
+
+    def _s(self):
+        st = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(st.cuda_stream)
+
+    def set_y(self, ys):
+        flat = self.prob.pack_y(ys) if isinstance(ys, (list, tuple)) else np.asarray(ys, dtype=np.float32)
+        self.y[: flat.size].copy_(self.torch.from_numpy(flat))
+
+    def set_params(self, thetas):
+        self.params[: self.n_micro].copy_(self.torch.from_numpy(self.prob.pack_micro(thetas)))
+        self.params[self.n_micro:].copy_(self.torch.from_numpy(self.prob.pack_cal(thetas)))
+
+    def reset_optimizer(self):
+        self.m.zero_()
+        self.v.zero_()
+        self.step.zero_()
+
+    def ptrs(self):
+        p = self.params.data_ptr()
+        g = self.grad.data_ptr()
+        return p, p + 4 * self.n_micro, g, g + 4 * self.n_micro
+
+    def loss_grad(self):
+        pm, pc, gm, gc = self.ptrs()
+        self.prob.loss_grad_ptr(self.y.data_ptr(), pm, pc, self.loss.data_ptr(), gm, gc,
+                                self.ws.data_ptr(), self.ws_bytes, self.status.data_ptr(), self._s())
+
+    def adam(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
+        n = self.n_micro + self.n_cal
+        adam_step_ptr(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                      n, lr, beta1, beta2, eps, self.step.data_ptr(), self._s())
+
+    def iteration(self, lr=1e-2):
+        self.loss_grad()
+        self.adam(lr)
+
+    def synthesize(self, out=None):
+        if out is None:
+            out = self.torch.empty(max(self.n_y, 1), dtype=self.torch.float32, device=self.device)
+        pm, pc, _, _ = self.ptrs()
+        self.prob.synthesize_ptr(pm, pc, out.data_ptr(), self._s())
+        return out
+
+    # host views
+    def grads_host(self):
+        g = self.grad.cpu().numpy()
+        return self.prob.unpack_micro(g[: self.n_micro]), self.prob.unpack_cal(g[self.n_micro:])
+
+    def params_host(self):
+        p = self.params.cpu().numpy()
+        return self.prob.unpack_micro(p[: self.n_micro]), self.prob.unpack_cal(p[self.n_micro:])
+
+    def loss_host(self):
+        return self.loss.cpu().numpy()

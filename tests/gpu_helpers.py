@@ -1,0 +1,124 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and the FP64 oracle on the same seeded inputs, and compare them."""
+from __future__ import annotations
+
+import dataclasses
+import sys
+
+import numpy as np
+
+import oracle as O
+from paper_2604_00250_amd import inputs as I
+
+LOSS_RTOL = 1e-5      # relative error of the total loss (FP32 kernels vs FP64 oracle)
+GRAD_RTOL = 1e-4      # normwise per parameter class: max|g - g_ref| / max|g_ref|
+
+CLASSES = {
+    "s0": ("s0",), "fractions": ("logits",), "directions": ("v",), "f_intra": ("fin",),
+    "diffusivities": ("dpar", "dperp"), "bias": ("bias",), "alpha": ("alpha",), "beta": ("beta",),
+    "sigma": ("sigma_log",),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_problem(g: I.Group, norm_count=None, coords=None) -> O.Problem:
+    return O.Problem(coords=g.coords if coords is None else coords, shape=tuple(g.shape),
+                     bval=np.asarray(g.acq.bval, dtype=np.float64),
+                     bvec=np.asarray(g.acq.bvec, dtype=np.float64), K=g.K, mode=g.mode, bias=g.bias,
+                     learn_diffusivity=g.learn_diffusivity, neighbourhood=g.neighbourhood,
+                     priors=tuple(g.priors), norm_count=norm_count)
+
+
+def theta64(th):
+    return {k: np.asarray(v, dtype=np.float64) for k, v in th.items()}
+
+
+def theta32(th):
+    """The float32 parameters both sides evaluate (the oracle gets them exactly)."""
+    return {k: np.asarray(np.asarray(v, dtype=np.float32), dtype=np.float64) for k, v in th.items()}
+
+
+def run_oracle(g: I.Group, th: dict):
+    prob = oracle_problem(g)
+    y = np.asarray(g.y, dtype=np.float64)
+    out, grad, yhat = O.loss_grad(prob, theta32(th), y)
+    return out, grad, yhat
+
+
+def run_gpu(groups, thetas, launch=None, repeat=1):
+    from paper_2604_00250_amd.problem import DeviceState, Problem
+    import torch
+    prob = Problem(groups, launch=launch)
+    st = DeviceState(prob, ys=[g.y for g in groups], thetas=thetas)
+    for _ in range(repeat):
+        st.loss_grad()
+    torch.cuda.synchronize()
+    gm, gc = st.grads_host()
+    loss = st.loss_host()
+    status = int(st.status.cpu().item())
+    return dict(prob=prob, state=st, loss=loss, gmicro=gm, gcal=gc, status=status)
+
+
+def merged_grad(gm, gc):
+    d = dict(gm)
+    d.update(gc)
+    return d
+
+
+def class_errors(g_gpu: dict, g_ref: dict):
+    errs = {}
+    for cls, keys in CLASSES.items():
+        a = [np.asarray(g_gpu[k], dtype=np.float64).ravel() for k in keys if k in g_ref and k in g_gpu]
+        b = [np.asarray(g_ref[k], dtype=np.float64).ravel() for k in keys if k in g_ref and k in g_gpu]
+        if not a:
+            continue
+        a, b = np.concatenate(a), np.concatenate(b)
+        if b.size == 0:
+            continue
+        scale = np.abs(b).max()
+        errs[cls] = float(np.abs(a - b).max() / scale) if scale > 0 else float(np.abs(a).max())
+    return errs
+
+
+def assert_parity(name, loss_gpu_row, g_gpu, out_ref, g_ref, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTOL):
+    terms = ("data", "spatial", "rep", "sparse", "cal", "total")
+    tot_ref = out_ref["total"]
+    rel = abs(loss_gpu_row[5] - tot_ref) / max(abs(tot_ref), 1e-300)
+    errs = class_errors(g_gpu, g_ref)
+    say(f"[{name}] loss gpu={loss_gpu_row[5]:.10g} ref={tot_ref:.10g} rel={rel:.2e} "
+        + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+    for i, t in enumerate(terms[:-1]):
+        ref = out_ref[t]
+        assert abs(loss_gpu_row[i] - ref) <= loss_rtol * max(abs(tot_ref), abs(ref)) + 1e-12, (name, t, loss_gpu_row[i], ref)
+    assert rel <= loss_rtol, (name, rel)
+    for cls, e in errs.items():
+        assert e <= grad_rtol, (name, cls, e)
+    return rel, errs
+
+
+def masked_group(shape, K, mode, seed, acq_kind="two96", bias="poly2", fill=0.7, learn=False,
+                 nbh=6, priors=I.PRIOR_NAMES, snr=25.0):
+    """A group with a random mask and a ragged voxel count, truth from the generator."""
+    rng = np.random.default_rng(seed)
+    acq = I.make_acquisition(acq_kind, rng)
+    mask = rng.random(shape) < fill
+    mask.reshape(-1)[0] = True
+    V = int(mask.sum())
+    truth = I.tissue_truth(V, rng, max_fib=min(K, 3))
+    S = I.truth_signal(acq, truth)
+    sigma = 1.0 / snr
+    y = I.rician(S, sigma, rng)
+    nb = {"none": 0, "poly2": 10, "trilinear8": 512}[bias]
+    th = I.init_theta(V, K, acq.n, nb, rng, sigma_init=2 * sigma if mode == "nll" else 0.0,
+                      learn_diffusivity=learn)
+    th = I.perturb_theta(th, rng, scale=0.7)
+    return I.Group(shape=shape, mask=mask, acq=acq, K=K, mode=mode, bias=bias, learn_diffusivity=learn,
+                   neighbourhood=nbh, priors=tuple(priors), y=y, theta=th, sigma_true=sigma)
+
+
+def with_theta(g: I.Group, th: dict) -> I.Group:
+    return dataclasses.replace(g, theta=th)
