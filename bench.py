@@ -1,0 +1,345 @@
+"""Benchmark of the PRISM fused analysis-by-synthesis iteration on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Workload: the whole-brain-shaped volume (145x174x145 grid, ~741k masked
+voxels, N = 288 three-shell measurements, K = 3, MSE mode, calibration on at
+identity, all priors), synthetic data from paper_2604_00250_amd.inputs.
+A step is one full iteration: the fused forward + adjoint pass with the
+spatial prior and the calibration reductions (prism_loss_grad) and the Adam
+update of every parameter (prism_adam_step), with y, parameters, moments and
+workspace resident in HBM.  Prints one JSON line.
+
+Extra legs (on by default, rank 0 only):
+  roofline       fused-kernel time from HIP events recorded by the library
+                 around each launch on the timed stream, against the VALU
+                 issue roofline built from the microbenchmarked exp cost;
+  cpu_baseline   the FP64 oracle on a bounded sample of the same volume, on
+                 the host cores (a process pool, one thread each);
+  torch_autograd the same objective written as plain per-op PyTorch FP32
+                 autograd (+ torch.optim.Adam) on the same GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autograd; %VALU"
+
+# Algorithmic work of one (voxel, measurement) pair of the fused pass at K = 3,
+# MSE, fixed diffusivities (counted from the pass's arithmetic, FMA = 1):
+#   forward 10K + 8 VALU and 2K exps, adjoint 12K + 10 VALU -> 84 VALU + 6 exp.
+ALG_VALU_PER_PAIR = 84
+ALG_EXP_PER_PAIR = 6
+# Algorithmic HBM bytes of one voxel of the fused pass: y (4N) + theta (4P) + gradient (4P)
+N_MEAS, P_VOX = 288, 17
+ALG_BYTES_PER_VOXEL = 4 * N_MEAS + 8 * P_VOX
+# MI355X issue capacity: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instruction slots / s
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------
+# plain PyTorch autograd baseline of the same objective (FP32, per-op)
+# ----------------------------------------------------------------------------
+
+def torch_objective(T, th, y, G, b, Phi, nbr, cnt, M, K, consts):
+    """Eq. 3-8 + priors of Sec. 2.4 with torch ops; th holds leaf tensors."""
+    torch = T
+    S0 = torch.nn.functional.softplus(th["s0"])
+    f = torch.softmax(th["logits"], dim=0)
+    d = th["v"] / th["v"].norm(dim=1, keepdim=True)
+    fin = torch.sigmoid(th["fin"])
+    logB = Phi.t() @ th["bias"]
+    S = (f[0][None] * torch.exp(-b * consts["d_csf"]) + f[1][None] * torch.exp(-b * consts["d_gm"])
+         + f[K + 2][None] * torch.exp(-b * consts["d_res"]))
+    for k in range(K):
+        c = G @ d[k]
+        c2 = c * c
+        e1 = torch.exp(-b * consts["d_par"] * c2)
+        e2 = torch.exp(-b * consts["d_perp"] * (1.0 - c2))
+        S = S + f[2 + k][None] * (fin[None] * e1 + (1.0 - fin[None]) * e1 * e2)
+    yhat = torch.exp(th["alpha"])[:, None] * torch.exp(logB)[None] * S0[None] * S + th["beta"][:, None]
+    data = ((yhat - y) ** 2).sum() / M
+    fpad = torch.cat([f, torch.zeros_like(f[:, :1])], 1)
+    mean = fpad[:, nbr].sum(-1) / cnt.clamp(min=1)[None]
+    r = torch.where(cnt[None] > 0, f - mean, torch.zeros_like(f))
+    a = r.abs()
+    dl = consts["huber_delta"]
+    spatial = torch.where(a <= dl, 0.5 * r * r, dl * (a - 0.5 * dl)).sum() * consts["lam_sp"] / M
+    rep = 0.0
+    fw = f[2:2 + K]
+    for i in range(K):
+        for j in range(i + 1, K):
+            rep = rep + (fw[i] * fw[j] * (d[i] * d[j]).sum(0).abs()).sum()
+    rep = rep * consts["lam_rep"] / M
+    sparse = (fw * (fw < consts["tau_sparse"]).to(fw.dtype)).sum() * consts["lam_sparse"] / M
+    cal = (consts["lam_alpha"] * (th["alpha"] ** 2).sum() + consts["lam_beta"] * (th["beta"] ** 2).sum()
+           + consts["lam_bias"] * (th["bias"] ** 2).sum())
+    return data + spatial + rep + sparse + cal
+
+
+def torch_baseline(g, y_dev, steps=5, warmup=2):
+    import numpy as np
+    import torch
+    dev = y_dev.device
+    consts = dict(d_csf=3.0, d_gm=0.9, d_res=0.2, d_par=1.7, d_perp=0.4, lam_sp=0.01, huber_delta=0.05,
+                  lam_rep=0.01, lam_sparse=0.02, tau_sparse=0.15, lam_alpha=0.01, lam_beta=0.01, lam_bias=0.01)
+    V = g.n_vox
+    coords = g.coords
+    shape = g.shape
+    xi = np.zeros((V, 3))
+    for a in range(3):
+        xi[:, a] = (2.0 * coords[:, a] - (shape[a] - 1)) / (shape[a] - 1)
+    x_, y_, z_ = xi.T
+    Phi = np.stack([np.ones(V), x_, y_, z_, x_ * x_, y_ * y_, z_ * z_, x_ * y_, x_ * z_, y_ * z_])
+    grid = -np.ones(shape, dtype=np.int64)
+    grid[tuple(coords.T)] = np.arange(V)
+    nbr = np.full((V, 6), V, dtype=np.int64)
+    for j, (dx, dy, dz) in enumerate([(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]):
+        c = coords + np.array([dx, dy, dz])
+        ok = np.all((c >= 0) & (c < np.array(shape)), 1)
+        idx = np.full(V, -1)
+        idx[ok] = grid[tuple(c[ok].T)]
+        nbr[:, j] = np.where(idx >= 0, idx, V)
+    cnt = (nbr < V).sum(1)
+    f32 = dict(dtype=torch.float32, device=dev)
+    th = {k: torch.tensor(np.asarray(v, dtype=np.float32), **f32).requires_grad_(True)
+          for k, v in g.theta.items() if k != "sigma_log"}
+    G = torch.tensor(g.acq.bvec, **f32)
+    bb = torch.tensor(g.acq.bval, **f32)[:, None]
+    Phi_t = torch.tensor(Phi, **f32)
+    nbr_t = torch.tensor(nbr, device=dev)
+    cnt_t = torch.tensor(cnt, **f32)
+    opt = torch.optim.Adam(list(th.values()), lr=1e-2)
+
+    def fwd_bwd():
+        for p in th.values():
+            p.grad = None
+        loss = torch_objective(torch, th, y_dev, G, bb, Phi_t, nbr_t, cnt_t, float(V), g.K, consts)
+        loss.backward()
+        return loss
+
+    res = {}
+    for label, with_opt in (("fwd_adjoint", False), ("iteration", True)):
+        for _ in range(warmup):
+            fwd_bwd()
+            if with_opt:
+                opt.step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fwd_bwd()
+            if with_opt:
+                opt.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[label] = dict(ms=ms, value=V / (ms * 1e-3))
+    res["peak_mem_GB"] = torch.cuda.max_memory_allocated(dev) / 1e9
+    del th, opt
+    torch.cuda.empty_cache()
+    return res
+
+
+# ----------------------------------------------------------------------------
+# FP64 oracle on the host cores (bounded sample)
+# ----------------------------------------------------------------------------
+
+_CPU_JOB = {}
+
+
+def _oracle_chunk(args):
+    lo, hi = args
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    threadpool_limits(1)
+    g = _CPU_JOB["g"]
+    prob = O.Problem(coords=g.coords[lo:hi], shape=g.shape, bval=g.acq.bval, bvec=g.acq.bvec, K=g.K,
+                     mode=g.mode, bias=g.bias, priors=tuple(g.priors), norm_count=g.n_vox)
+    th = {k: (np.asarray(v, np.float64)[..., lo:hi] if k not in ("bias", "alpha", "beta", "sigma_log")
+              else np.asarray(v, np.float64)) for k, v in g.theta.items()}
+    t = time.perf_counter()
+    O.loss_grad(prob, th, np.asarray(g.y[:, lo:hi], np.float64))
+    return hi - lo, time.perf_counter() - t
+
+
+def cpu_baseline(g, target_s=10.0, chunk=4096):
+    """The oracle's loss_grad over chunks of the volume's voxels, one process
+    per host core (each single-threaded), for about `target_s` seconds."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    _CPU_JOB["g"] = g
+    n, t1 = _oracle_chunk((0, chunk))     # calibrate one chunk in this process
+    per_chunk = t1
+    n_chunks = max(cores, int(target_s * cores / per_chunk))
+    n_chunks = min(n_chunks, g.n_vox // chunk)
+    jobs = [(i * chunk, (i + 1) * chunk) for i in range(n_chunks)]
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        done = pool.map(_oracle_chunk, jobs, chunksize=1)
+    wall = time.perf_counter() - t
+    vox = sum(d[0] for d in done)
+    return dict(value=vox / wall, unit="voxel-iters/s", cores=cores, kind="oracle",
+                sample=f"{n_chunks} chunks x {chunk} voxels ({vox} voxel-iterations of loss+gradient, "
+                       f"N=288, K=3, FP64 NumPy, one process per core), {wall:.1f} s wall",
+                seconds_per_chunk_single_core=per_chunk)
+
+
+# ----------------------------------------------------------------------------
+# main
+# ----------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-torch-baseline", action="store_true")
+    ap.add_argument("--no-microbench", action="store_true")
+    ap.add_argument("--launch", type=str, default="", help="vox_per_lane,n_split,item_vox")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures the single-GPU path only: this build runs the fused pass on one "
+              "MI355X (multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    from paper_2604_00250_amd import inputs as I
+
+    t0 = time.time()
+    w = I.config2()
+    g = w.groups[0]
+    log(f"workload {w.name}: {g.n_vox} voxels, N={g.acq.n}, K={g.K}, generated in {time.time() - t0:.1f} s")
+    # the CPU leg runs first, in worker processes forked before this process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(g)
+    if cpu:
+        log(f"cpu baseline: {cpu['value']:.4g} voxel-iters/s on {cpu['cores']} cores")
+
+    import torch
+    from paper_2604_00250_amd.problem import DeviceState, Problem
+    launch = None
+    if args.launch:
+        vpl, ns, iv = (int(x) for x in args.launch.split(","))
+        launch = dict(vox_per_lane=vpl, n_split=ns, item_vox=iv)
+    prob = Problem([g], launch=launch)
+    st = DeviceState(prob, ys=[g.y], thetas=[g.theta], device="cuda:0")
+    V = g.n_vox
+
+    for _ in range(args.warmup):
+        st.iteration(lr=w.lr)
+    torch.cuda.synchronize()
+    prob.profile(True, max_launches=args.steps + 4)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        st.iteration(lr=w.lr)
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    k_ms_total, k_launches = prob.profile_read()
+    prob.profile(False)
+    k_ms = k_ms_total / max(k_launches, 1)
+    status = int(st.status.cpu().item())
+    loss = st.loss_host()[0]
+    if status != 0 or not np.isfinite(loss[5]):
+        log(f"WARNING: status {status}, loss {loss}")
+
+    # fwd+adjoint only (prism_loss_grad), same state
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        st.loss_grad()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fa = e0.elapsed_time(e1) / args.steps
+
+    pairs = V * g.acq.n
+    mb = None
+    if not args.no_microbench:
+        try:
+            from paper_2604_00250_amd import microbench
+            mb = microbench.run()
+        except Exception as ex:  # the roofline still reports with q = 1
+            log(f"microbenchmark failed: {ex}")
+    q = mb["q_exp"] if mb else 1.0
+    slots = pairs * (ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR)
+    achieved = slots / (k_ms * 1e-3)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
+                    frac=achieved / PEAK_SLOTS, traffic=None,
+                    kernel="k_pass<3,MSE,fixedD>", kernel_ms=k_ms, launches=k_launches,
+                    alg_slots_per_pair=ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR, q_exp=q,
+                    hbm_GBps=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / 1e9,
+                    hbm_frac=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / PEAK_HBM)
+    out = {
+        "metric": METRIC,
+        "value": V / (ms * 1e-3),
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "voxels": V, "grid": list(g.shape), "measurements": g.acq.n,
+                   "K": g.K, "mode": "mse", "priors": list(g.priors), "bias": g.bias,
+                   "launch": prob.launch(), "step": "prism_loss_grad + prism_adam_step"},
+        "fwd_adjoint": {"value": V / (ms_fa * 1e-3), "ms": ms_fa},
+        "roofline": roofline,
+        "wall_s_timed": t_wall,
+        "loss": float(loss[5]),
+        "status": status,
+        "paper_context": "~741k voxels x 100 iterations per slab in ~12 min on one RTX A6000 "
+                         "(about 1e5 voxel-iters/s, MSE; a different machine and workload)",
+    }
+    if mb:
+        out["microbench"] = mb
+    if not args.no_torch_baseline:
+        try:
+            tb = torch_baseline(g, st.y[: g.acq.n * V].view(g.acq.n, V))
+            out["torch_autograd"] = dict(value=tb["iteration"]["value"], ms=tb["iteration"]["ms"],
+                                         fwd_adjoint_value=tb["fwd_adjoint"]["value"],
+                                         fwd_adjoint_ms=tb["fwd_adjoint"]["ms"],
+                                         peak_mem_GB=tb["peak_mem_GB"],
+                                         speedup_iteration=out["value"] / tb["iteration"]["value"],
+                                         speedup_fwd_adjoint=out["fwd_adjoint"]["value"] / tb["fwd_adjoint"]["value"])
+        except Exception as ex:
+            log(f"torch baseline failed: {ex}")
+            out["torch_autograd"] = {"error": str(ex)[:200]}
+    del st
+    torch.cuda.empty_cache()
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

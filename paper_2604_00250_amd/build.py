@@ -54,6 +54,13 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    # roofline microbenchmarks (a separate small library; the product path never loads it)
+    mb = os.path.join(HERE, "libprism_mb.so")
+    cmd = [hipcc()] + flags + ["-shared", os.path.join(CSRC, "microbench.hip"), "-o", mb + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"microbenchmark build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(mb + ".tmp", mb)
     return LIB
 
 

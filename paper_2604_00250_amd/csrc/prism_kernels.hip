@@ -238,7 +238,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
       sd *= valid;
       ds *= valid;
     }
-    seed = copysignf(sd, yh);
+    seed = yh < 0.0f ? -sd : sd;           // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
     lacc += term;
     sacc += ds;
   }
@@ -850,14 +850,22 @@ __global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* t
 // ---------------------------------------------------------------------------
 // optimisers
 // ---------------------------------------------------------------------------
+// Adam, PyTorch's form; t = step[0] + 1 is read by every block and the step
+// counter is advanced afterwards by k_step_advance (stream order), so no
+// block waits on another and no counter is contended.
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float b1, float b2,
+                                         float eps, float step_size, float ibc2) {
+  m = fmaf(1.0f - b1, g - m, m);
+  v = fmaf(1.0f - b2, g * g, v * b2);
+  p = p - step_size * (m / fmaf(sqrtf(v), ibc2, eps));
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
                                               int64_t n, float lr, float b1, float b2, float eps,
-                                              int32_t* step) {
+                                              const int32_t* step, int vec4) {
   __shared__ float sc[2];
-  __shared__ int tcur;
   if (threadIdx.x == 0) {
     const int t = step[0] + 1;
-    tcur = t;
     const double bc1 = 1.0 - pow((double)b1, (double)t);
     const double bc2 = 1.0 - pow((double)b2, (double)t);
     sc[0] = (float)((double)lr / bc1);
@@ -866,24 +874,40 @@ __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m
   __syncthreads();
   const float step_size = sc[0], ibc2 = sc[1];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float gi = g[i];
-    float mi = m[i], vi = v[i];
-    mi = fmaf(1.0f - b1, gi - mi, mi);
-    vi = fmaf(1.0f - b2, gi * gi, vi * b2);
-    const float denom = fmaf(sqrtf(vi), ibc2, eps);
-    p[i] = p[i] - step_size * (mi / denom);
-    m[i] = mi;
-    v[i] = vi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(&step[1], 1);
-    if (prev == (int)gridDim.x - 1) {
-      atomicExch(&step[0], tcur);
-      atomicExch(&step[1], 0);
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t done = 0;
+  if (vec4) {
+    const int64_t n4 = n >> 2;
+    float4* p4 = reinterpret_cast<float4*>(p);
+    const float4* g4 = reinterpret_cast<const float4*>(g);
+    float4* m4 = reinterpret_cast<float4*>(m);
+    float4* v4 = reinterpret_cast<float4*>(v);
+    for (int64_t i = tid; i < n4; i += stride) {
+      float4 pp = p4[i], mm = m4[i], vv = v4[i];
+      const float4 gg = g4[i];
+      adam_one(pp.x, gg.x, mm.x, vv.x, b1, b2, eps, step_size, ibc2);
+      adam_one(pp.y, gg.y, mm.y, vv.y, b1, b2, eps, step_size, ibc2);
+      adam_one(pp.z, gg.z, mm.z, vv.z, b1, b2, eps, step_size, ibc2);
+      adam_one(pp.w, gg.w, mm.w, vv.w, b1, b2, eps, step_size, ibc2);
+      p4[i] = pp;
+      m4[i] = mm;
+      v4[i] = vv;
     }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + tid; i < n; i += stride) {
+    float pp = p[i], mm = m[i], vv = v[i];
+    adam_one(pp, g[i], mm, vv, b1, b2, eps, step_size, ibc2);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+  }
+}
+
+__global__ void k_step_advance(int32_t* step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    step[0] = step[0] + 1;
+    step[1] = 0;
   }
 }
 
@@ -976,11 +1000,17 @@ hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups,
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int32_t* step, hipStream_t s) {
-  int64_t blocks = (n + 1023) / 1024;
+  const bool vec4 = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) |
+                      reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  int64_t blocks = (n + 2047) / 2048;
   if (blocks < 1) blocks = 1;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
-                     eps, step);
+  if (blocks > 4096) blocks = 4096;
+  if (n > 0)
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
+                       eps, step, vec4 ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
   return hipGetLastError();
 }
 

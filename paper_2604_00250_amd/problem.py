@@ -104,9 +104,9 @@ class Problem:
     def pack_micro(self, thetas: Sequence[dict]) -> np.ndarray:
         out = np.zeros(self.info.n_micro, dtype=np.float32)
         for g, gi, th in zip(self.groups, self.ginfo, thetas):
-            V = int(gi.n_vox)
-            rows = [np.asarray(th["s0"]).reshape(1, V), np.asarray(th["logits"]).reshape(-1, V),
-                    np.asarray(th["v"]).reshape(-1, V), np.asarray(th["fin"]).reshape(1, V)]
+            V, C = int(gi.n_vox), g.K + 3
+            rows = [np.asarray(th["s0"]).reshape(1, V), np.asarray(th["logits"]).reshape(C, V),
+                    np.asarray(th["v"]).reshape(3 * g.K, V), np.asarray(th["fin"]).reshape(1, V)]
             if g.learn_diffusivity:
                 rows += [np.asarray(th["dpar"]).reshape(1, V), np.asarray(th["dperp"]).reshape(1, V)]
             blk = np.concatenate(rows, 0).astype(np.float32)
@@ -135,7 +135,7 @@ class Problem:
         res = []
         for g, gi in zip(self.groups, self.ginfo):
             V, K = int(gi.n_vox), g.K
-            blk = np.asarray(flat[gi.micro_offset:gi.micro_offset + gi.n_params_vox * V]).reshape(-1, V)
+            blk = np.asarray(flat[gi.micro_offset:gi.micro_offset + gi.n_params_vox * V]).reshape(gi.n_params_vox, V)
             C = K + 3
             d = dict(s0=blk[0], logits=blk[1:1 + C], v=blk[1 + C:1 + C + 3 * K].reshape(K, 3, V),
                      fin=blk[1 + C + 3 * K])
