@@ -371,10 +371,13 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
       grid.insert(grid.end(), idx.begin(), idx.end());
       h->tri_groups.push_back(gi);
     }
-    g.w_off = wfl;
-    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += (int64_t)g.C * V;
+    g.w_off = wfl;  // [C][V] residual weights, then [C][V] fractions
+    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += 2 * (int64_t)g.C * V;
     g.glb_off = wfl;
     if (d.bias == PRISM_BIAS_TRILINEAR8) wfl += V;
+    wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned acquisition table
+    g.acqtab_off = wfl;
+    wfl += (int64_t)kAcqStride * g.N;
     micro += (int64_t)g.P * V;
     cal += g.n_bias + 2 * g.N + 1;
     y += (int64_t)g.N * V;
@@ -391,7 +394,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   h->ws_float = (size_t)wfl;
   h->acq_off = acq_off;
   // default launch shape: split measurements across waves for small problems
-  h->launch.vox_per_lane = 1;
+  h->launch.vox_per_lane = vox >= 262144 ? 2 : 1;
   h->launch.n_split = vox < 65536 ? 4 : (vox < 262144 ? 2 : 1);
   h->launch.item_vox = 0;
   hipError_t e = upload(&h->d_bval, bval);
@@ -531,7 +534,8 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
   double* part = (double*)(ws + align256(h->ws_rec * sizeof(double)));
   float* wsp = (float*)(ws + align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)));
   PassArgs a = pass_args(h, y, theta_micro, theta_cal, grad_micro, rec, wsp, status);
-  hipError_t e = hipSuccess;
+  hipError_t e = launch_stage(a, (int)h->groups.size(), s);
+  if (e != hipSuccess) return hip_fail(e, "acquisition staging launch");
   if (!h->items.empty()) {
     a.item_base = 0;
     a.n_items = (int)h->items.size();

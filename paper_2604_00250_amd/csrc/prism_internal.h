@@ -34,6 +34,7 @@ struct GroupDev {
   int64_t glb_off;    // float offset of per-voxel dL/dlogB [V] in the workspace (trilinear)
   int64_t rec_off;    // float64 offset of the group's first item record
   int64_t grid_off;   // int32 offset of the dense raster->voxel index grid (trilinear)
+  int64_t acqtab_off; // float offset of the staged acquisition table [N][12] in the workspace
   int32_t V, N, K, C, P;
   int32_t mode, bias, n_bias, learn_d, nbh, priors;
   int32_t nx, ny, nz;
@@ -74,7 +75,7 @@ struct PassArgs {
   const float* th_cal;
   float* g_micro;
   double* rec;
-  float* wsp;              // workspace floats (spatial weights, per-voxel dlogB)
+  float* wsp;              // workspace floats (spatial weights, per-voxel dlogB, acquisition tables)
   uint32_t* status;
   ModelDev model;
   int32_t item_base;       // first item of this launch
@@ -103,6 +104,7 @@ struct ReduceArgs {
 
 // launchers (prism_kernels.hip)
 hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s);
+hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
                             hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int max_tile_fields, hipStream_t s);

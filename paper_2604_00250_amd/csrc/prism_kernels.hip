@@ -15,6 +15,27 @@
 
 namespace prism {
 
+#ifndef PRISM_PASS_MIN_WAVES
+#define PRISM_PASS_MIN_WAVES 1
+#endif
+#ifndef PRISM_STEP_BARRIER
+#define PRISM_STEP_BARRIER 0
+#endif
+#ifndef PRISM_TILE
+#define PRISM_TILE 16
+#endif
+#ifndef PRISM_ACQ_SMEM
+#define PRISM_ACQ_SMEM 0
+#endif
+#ifndef PRISM_PREFETCH
+#define PRISM_PREFETCH 4
+#endif
+// measurements per matrix-core reduction tile (8 or 16 columns of the 16x16 tile)
+constexpr int kTile = PRISM_TILE;
+// depth of the y prefetch ring (measurements ahead); kTile is a multiple of it
+constexpr int kPf = PRISM_PREFETCH;
+static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
+
 enum { kMSE = 0, kNLL = 1 };
 enum { kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8 };
 enum { kStNonfiniteLoss = 1, kStNonfiniteGrad = 2, kStZeroDir = 4 };
@@ -39,6 +60,13 @@ __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* 
                                  expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
     acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b * dpar, 2.0f * b * dperp);
   }
+}
+
+// The same table written once per call to the workspace, read by the fused
+// pass through the scalar cache (uniform loads into SGPRs).
+__global__ __launch_bounds__(256) void k_stage(PassArgs A) {
+  const GroupDev g = A.groups[blockIdx.x];
+  stage_acquisition(A, g, reinterpret_cast<float4*>(A.wsp + g.acqtab_off));
 }
 
 // ---------------------------------------------------------------------------
@@ -125,7 +153,10 @@ __device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, i
   return s;
 }
 
-// Prologue: raw parameters of voxel v -> constrained quantities (Sec. 2.2, 2.5).
+// Raw parameters of voxel v -> constrained quantities (Sec. 2.2, 2.5).  Called
+// in the prologue (Vox for the measurement loop) and again in the epilogue
+// (Derived for the chain rule), so that nothing but Vox stays live across the
+// measurement loop.
 template <int K, bool LD>
 __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g, int v,
                                            Vox<K, LD>& x, Derived& dv, bool& zero_dir) {
@@ -193,15 +224,15 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
 // ---------------------------------------------------------------------------
 // one (voxel, measurement) pair: forward, data term, adjoint accumulation
 // ---------------------------------------------------------------------------
-template <int K, int MODE, bool LD, bool MASKED>
+template <int K, int MODE, bool LD>
 __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv,
-                                     const float4 a, const float4 b, const float4 c, float valid,
-                                     float inv_s2, float& lacc, float& sacc, float& pa, float& pb) {
+                                     const float4 a, const float4 b, const float4 c, float inv_s2,
+                                     float& t_loss, float& t_sig, float& sq, float& seed) {
   const float gx = a.x, gy = a.y, gz = a.z;
   float S = x.F[0] * b.y;
   S = fmaf(x.F[1], b.z, S);
   S = fmaf(x.F[K + 2], b.w, S);
-  float cc[K], e1[K], e2[K], oe[K], h[K], E[K];
+  float cc[K], e1[K], e2[K], h[K], E[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     cc[k] = fmaf(gz, x.d[k][2], fmaf(gy, x.d[k][1], gx * x.d[k][0]));
@@ -210,43 +241,34 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
     const float kq = LD ? b.x * x.dperp : b.x;
     e1[k] = ex2(kp * c2);                 // exp(-b Dpar cos^2)
     e2[k] = ex2(fmaf(-kq, c2, kq));       // exp(-b Dperp sin^2)
-    oe[k] = x.omf * e2[k];
-    h[k] = x.fin + oe[k];
+    h[k] = fmaf(x.omf, e2[k], x.fin);     // f_intra + (1 - f_intra) e2
     E[k] = e1[k] * h[k];                  // Eq. 5
     S = fmaf(x.F[2 + k], E[k], S);        // Eq. 3
   }
   const float AB = c.x * x.B;
   const float q = AB * S;                 // yhat - beta
   const float yh = q + c.y;               // Eq. 6
-  float seed;
   if (MODE == kMSE) {
-    float r = yh - yv;
-    if (MASKED) r *= valid;
+    const float r = yh - yv;
     seed = r;
-    lacc = fmaf(r, r, lacc);
+    t_loss = r * r;
+    t_sig = 0.0f;
   } else {
     const float ay = fabsf(yv), ah = fabsf(yh);
     const float z = ay * ah * inv_s2;
     float omr;
     const float li = log_i0e(z, omr);
     const float dd = ah - ay;
-    float term = fmaf(dd * dd, 0.5f * inv_s2, -li);
-    float sd = fmaf(ay, omr, dd) * inv_s2;
-    float ds = fmaf(dd * dd, inv_s2, 2.0f * z * omr);
-    if (MASKED) {
-      term *= valid;
-      sd *= valid;
-      ds *= valid;
-    }
-    seed = yh < 0.0f ? -sd : sd;           // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
-    lacc += term;
-    sacc += ds;
+    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li);
+    t_sig = fmaf(dd * dd, inv_s2, 2.0f * z * omr);
+    const float sd = fmaf(ay, omr, dd) * inv_s2;
+    seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
   }
-  const float sq = seed * q;
-  pa += sq;
-  pb += seed;
+  sq = seed * q;
   acc.r[Acc<K, LD>::kLogB] += sq;
   const float dS = seed * AB;
+  // Q2 (1 - f_intra), shared by the K fibres
+  const float q2o = (LD ? c.w * x.dperp : c.w) * x.omf;
   acc.r[0] = fmaf(dS, b.y, acc.r[0]);
   acc.r[1] = fmaf(dS, b.z, acc.r[1]);
   acc.r[K + 2] = fmaf(dS, b.w, acc.r[K + 2]);
@@ -257,9 +279,8 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
     const float e12 = e1[k] * e2[k];
     acc.r[Acc<K, LD>::kFin] = fmaf(dE, e1[k] - e12, acc.r[Acc<K, LD>::kFin]);
     const float p2 = LD ? c.z * x.dpar : c.z;
-    const float q2 = LD ? c.w * x.dperp : c.w;
     // dE/dcos = cos e1 (P2 h + Q2 (1-fin) e2)
-    const float t = fmaf(q2, oe[k], p2 * h[k]);
+    const float t = fmaf(q2o, e2[k], p2 * h[k]);
     const float dc = dE * (cc[k] * e1[k]) * t;
     acc.r[Acc<K, LD>::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[Acc<K, LD>::kGd + 3 * k + 0]);
     acc.r[Acc<K, LD>::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[Acc<K, LD>::kGd + 3 * k + 1]);
@@ -269,33 +290,113 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
       const float mb = 0.5f * c.z;
       const float c2 = cc[k] * cc[k];
       acc.r[Acc<K, LD>::kDpar] = fmaf(dE * E[k], mb * c2, acc.r[Acc<K, LD>::kDpar]);
-      acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe[k], mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
+      const float oe = x.omf * e2[k];
+      acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe, mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
     }
   }
 }
 
-constexpr int kLossFlush = 16;  // measurements summed in float32 before a float64 add
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------------------
-// fused pass
-// ---------------------------------------------------------------------------
+// Measurements [nb, ne) for the VL voxels of this lane, in tiles of kTile.
+// The per-measurement sums over the wave's 64 x VL voxels (the alpha_n and
+// beta_n adjoints) are accumulated on the matrix core: with A = this lane's
+// partial and B = the one-hot column t = n - n0, v_mfma_f32_16x16x4f32 adds
+// each lane's value into column t of a 16x16 tile; after the tile, lane l
+// holds rows 4(l/16)..4(l/16)+3 of column l%16, so four adds and two lane
+// exchanges give the wave total for measurement n0 + l%16.  Invalid lanes
+// (beyond the item) carry valid = 0, which removes them from every sum.
 template <int K, int MODE, bool LD, int VL>
-__global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
+__device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<K, LD> (&acc)[VL],
+                                                 const float* yg, int64_t V, const int (&vox)[VL],
+                                                 const float (&valid)[VL],
+                                                 const float4* __restrict__ acq,
+                                                 int nb, int ne, int N, float inv_s2, int lane,
+                                                 float* wacc, double& dloss, double& dsig) {
+  const int lane16 = lane & 15;
+  const float* yp[VL];
+#pragma unroll
+  for (int j = 0; j < VL; ++j) yp[j] = yg + vox[j];
+  // y prefetch ring kPf measurements deep (slot u holds measurement nb + u mod kPf)
+  float yr[kPf][VL];
+#pragma unroll
+  for (int u = 0; u < kPf; ++u)
+#pragma unroll
+    for (int j = 0; j < VL; ++j) yr[u][j] = yp[j][(int64_t)min(nb + u, ne - 1) * V];
+  for (int n0 = nb; n0 < ne; n0 += kTile) {
+    const int cnt = min(kTile, ne - n0);
+    v4f Da = {0.0f, 0.0f, 0.0f, 0.0f}, Db = {0.0f, 0.0f, 0.0f, 0.0f};
+    float lacc = 0.0f, sacc = 0.0f;
+    for (int t0 = 0; t0 < cnt; t0 += kPf) {
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int t = t0 + u;
+        if (t < cnt) {
+          const int n = n0 + t;
+          float yv[VL];
+#pragma unroll
+          for (int j = 0; j < VL; ++j) {
+            yv[j] = yr[u][j];
+            yr[u][j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: always in bounds
+          }
+          const float4 a = acq[3 * n + 0];
+          const float4 b = acq[3 * n + 1];
+          const float4 c = acq[3 * n + 2];
+          float pa = 0.0f, pb = 0.0f;
+#pragma unroll
+          for (int j = 0; j < VL; ++j) {
+            float tl, ts, sq, sd;
+            pair<K, MODE, LD>(x[j], acc[j], yv[j], a, b, c, inv_s2, tl, ts, sq, sd);
+            lacc = fmaf(valid[j], tl, lacc);
+            if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
+            pa = fmaf(valid[j], sq, pa);
+            pb = fmaf(valid[j], sd, pb);
+          }
+          const float sel = lane16 == t ? 1.0f : 0.0f;
+          Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
+          Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+        }
+      }
+    }
+    float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);
+    float rb = (Db[0] + Db[1]) + (Db[2] + Db[3]);
+    ra += __shfl_xor(ra, 16, 64);
+    rb += __shfl_xor(rb, 16, 64);
+    ra += __shfl_xor(ra, 32, 64);
+    rb += __shfl_xor(rb, 32, 64);
+    if (lane < cnt) {
+      wacc[n0 + lane] += ra;
+      wacc[N + n0 + lane] += rb;
+    }
+    dloss += (double)lacc;
+    dsig += (double)sacc;
+  }
+}
+
+template <int K, int MODE, bool LD, int VL>
+__global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
+    PassArgs A, const float4* __restrict__ acq_global) {
   extern __shared__ float4 smem4[];
   __shared__ double red[4][16];
   constexpr int C = K + 3;
   constexpr int NACC = Acc<K, LD>::N;
   const ItemDev it = A.items[A.item_base + blockIdx.x];
   const GroupDev g = A.groups[it.group];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
   const int WN = A.n_split, rows = 4 / WN;
   const int row = wave / WN, split = wave - row * WN;
   const int N = g.N;
-  float4* acq = smem4;
-  float* accab = reinterpret_cast<float*>(smem4 + 3 * N);  // [4][2][N]
+  float4* acq = smem4;                                       // [3N] unless read from SMEM
+  float* accab = reinterpret_cast<float*>(smem4 + (PRISM_ACQ_SMEM ? 0 : 3 * N));  // [4][2][N]
   float* xbuf = accab + 8 * N;                               // [rows][WN-1][NACC][64*VL]
 
+#if PRISM_ACQ_SMEM
+  const float4* __restrict__ acq_tab = acq_global + g.acqtab_off / 4;
+#else
   stage_acquisition(A, g, acq);
+  const float4* acq_tab = acq;
+#endif
   for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
   __syncthreads();
 
@@ -308,10 +409,15 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
   const bool has_sp = (g.priors & kPriorSpatial) && g.nbh > 0;
   float* wacc = accab + wave * 2 * N;
 
-  double dloss = 0.0, dsig = 0.0, drep = 0.0, dspa = 0.0;
-  float pbias[10];
+  double dloss = 0.0, dsig = 0.0;
+  // per-thread partials of the epilogue (repulsion, sparsity, quadratic-bias adjoint),
+  // parked in LDS so that they are not live across the measurement loop
+  __shared__ double ep_d[2][kBlock];
+  __shared__ float ep_b[10][kBlock];
+  ep_d[0][tid] = 0.0;
+  ep_d[1][tid] = 0.0;
 #pragma unroll
-  for (int j = 0; j < 10; ++j) pbias[j] = 0.0f;
+  for (int q = 0; q < 10; ++q) ep_b[q][tid] = 0.0f;
   bool bad_grad = false, zero_dir = false;
 
   const int chunk = 64 * VL * rows;
@@ -325,61 +431,18 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
       valid[j] = ok ? 1.0f : 0.0f;
       vox[j] = it.v0 + (ok ? lv : 0);
     }
-    const bool full = cb + chunk <= it.nv;
     Vox<K, LD> x[VL];
-    Derived dv[VL];
     Acc<K, LD> acc[VL];
 #pragma unroll
     for (int j = 0; j < VL; ++j) {
-      load_voxel<K, LD>(A, g, vox[j], x[j], dv[j], zero_dir);
+      Derived dv_unused;
+      load_voxel<K, LD>(A, g, vox[j], x[j], dv_unused, zero_dir);
 #pragma unroll
       for (int i = 0; i < NACC; ++i) acc[j].r[i] = 0.0f;
     }
 
-    // measurement loop with a 2-deep prefetch of y
-    float yb0[VL], yb1[VL];
-#pragma unroll
-    for (int j = 0; j < VL; ++j) {
-      yb0[j] = nb < ne ? yg[(int64_t)nb * V + vox[j]] : 0.0f;
-      yb1[j] = nb + 1 < ne ? yg[(int64_t)(nb + 1) * V + vox[j]] : 0.0f;
-    }
-    for (int n0 = nb; n0 < ne; n0 += kLossFlush) {
-      const int n1 = min(n0 + kLossFlush, ne);
-      float lacc = 0.0f, sacc = 0.0f;
-      for (int n = n0; n < n1; ++n) {
-        float ycur[VL];
-#pragma unroll
-        for (int j = 0; j < VL; ++j) {
-          ycur[j] = yb0[j];
-          yb0[j] = yb1[j];
-          yb1[j] = n + 2 < ne ? yg[(int64_t)(n + 2) * V + vox[j]] : 0.0f;
-        }
-        const float4 a = acq[3 * n + 0];
-        const float4 b = acq[3 * n + 1];
-        const float4 c = acq[3 * n + 2];
-        float pa = 0.0f, pb = 0.0f;
-        if (full) {
-#pragma unroll
-          for (int j = 0; j < VL; ++j)
-            pair<K, MODE, LD, false>(x[j], acc[j], ycur[j], a, b, c, 1.0f, inv_s2, lacc, sacc, pa,
-                                     pb);
-        } else {
-#pragma unroll
-          for (int j = 0; j < VL; ++j)
-            pair<K, MODE, LD, true>(x[j], acc[j], ycur[j], a, b, c, valid[j], inv_s2, lacc, sacc,
-                                    pa, pb);
-        }
-        // per-measurement sums over the wave's voxels (alpha_n, beta_n adjoints)
-        pa = wave_sum_to_63(pa);
-        pb = wave_sum_to_63(pb);
-        if (lane == 63) {
-          wacc[n] += pa;
-          wacc[N + n] += pb;
-        }
-      }
-      dloss += (double)lacc;
-      dsig += (double)sacc;
-    }
+    measurement_loop<K, MODE, LD, VL>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
+                                      wacc, dloss, dsig);
 
     // combine the per-voxel accumulators of the waves that split this row over n
     if (WN > 1) {
@@ -414,7 +477,12 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
       for (int j = 0; j < VL; ++j) {
         if (valid[j] == 0.0f) continue;
         const int v = vox[j];
-        const Derived& D = dv[j];
+        Derived D;
+        {
+          Vox<K, LD> x_again;
+          bool zd = false;
+          load_voxel<K, LD>(A, g, v, x_again, D, zd);
+        }
         float gF[C], gf[C];
         float gS0 = 0.0f;
 #pragma unroll
@@ -468,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
                 gd[k][a] = fmaf(w2, x[j].d[i][a], gd[k][a]);
               }
             }
-          drep += (double)lr;
+          ep_d[0][tid] += (double)lr;
         }
         if (g.priors & kPriorSparse) {
           float ls = 0.0f;
@@ -480,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
               gf[2 + k] += sc_spa;
             }
           }
-          dspa += (double)ls;
+          ep_d[1][tid] += (double)ls;
         }
         // softmax chain rule
         float gsum = 0.0f;
@@ -518,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
           const float zz = g.nz > 1 ? (2.0f * k - (g.nz - 1)) / (float)(g.nz - 1) : 0.0f;
           const float phi[10] = {1.0f, xx, yy, zz, xx * xx, yy * yy, zz * zz, xx * yy, xx * zz, yy * zz};
 #pragma unroll
-          for (int q = 0; q < 10; ++q) pbias[q] = fmaf(phi[q], glb, pbias[q]);
+          for (int q = 0; q < 10; ++q) ep_b[q][tid] = fmaf(phi[q], glb, ep_b[q][tid]);
         } else if (g.bias == 2) {
           A.wsp[g.glb_off + v] = glb;
         }
@@ -531,11 +599,11 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs A) {
   double* rec = A.rec + g.rec_off + (int64_t)it.rec * g.rec_stride;
   double vals[14];
   vals[0] = dloss;
-  vals[1] = drep;
-  vals[2] = dspa;
+  vals[1] = ep_d[0][tid];
+  vals[2] = ep_d[1][tid];
   vals[3] = dsig;
 #pragma unroll
-  for (int q = 0; q < 10; ++q) vals[4 + q] = (double)pbias[q];
+  for (int q = 0; q < 10; ++q) vals[4 + q] = (double)ep_b[q][tid];
 #pragma unroll
   for (int q = 0; q < 14; ++q) {
     const double s = wave_sum_f64(vals[q]);
@@ -621,6 +689,26 @@ __device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, in
     if (c < C) f[c] *= inv;
 }
 
+// fractions f = softmax(logits) once per voxel, into the weight buffer
+__global__ __launch_bounds__(kBlock) void k_fractions(PassArgs A) {
+  const ItemDev it = A.items[blockIdx.x];
+  const GroupDev g = A.groups[it.group];
+  if (!((g.priors & kPriorSpatial) && g.nbh > 0)) return;
+  const float* th = A.th_micro + g.micro_off;
+  const int64_t V = g.V;
+  const int C = g.C;
+  float* f_out = A.wsp + g.w_off + (int64_t)C * V;
+  for (int lv = threadIdx.x; lv < it.nv; lv += kBlock) {
+    const int v = it.v0 + lv;
+    float f[kMaxC];
+    softmax_at(th, V, C, v, f);
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c)
+      if (c < C) f_out[(int64_t)c * V + v] = f[c];
+  }
+}
+
+// Eq. 7 residual weights w_c(x) = rho'(r_c(x)) / |N(x)| from the stored fractions
 __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
   __shared__ double red[4];
   const ItemDev it = A.items[blockIdx.x];
@@ -628,15 +716,15 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
   const int tid = threadIdx.x;
   double lsum = 0.0;
   if ((g.priors & kPriorSpatial) && g.nbh > 0) {
-    const float* th = A.th_micro + g.micro_off;
     const int32_t* nbr = A.nbr + g.nbr_off;
     const int64_t V = g.V;
     const int C = g.C;
+    const float* fr = A.wsp + g.w_off + (int64_t)C * V;
+    float* w_out = A.wsp + g.w_off;
     const float delta = A.model.huber_delta;
     for (int lv = tid; lv < it.nv; lv += kBlock) {
       const int v = it.v0 + lv;
-      float f[kMaxC], mean[kMaxC], t[kMaxC];
-      softmax_at(th, V, C, v, f);
+      float mean[kMaxC];
 #pragma unroll
       for (int c = 0; c < kMaxC; ++c) mean[c] = 0.0f;
       int cnt = 0;
@@ -644,10 +732,9 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
         const int u = nbr[(int64_t)q * V + v];
         if (u >= 0) {
           ++cnt;
-          softmax_at(th, V, C, u, t);
 #pragma unroll
           for (int c = 0; c < kMaxC; ++c)
-            if (c < C) mean[c] += t[c];
+            if (c < C) mean[c] += fr[(int64_t)c * V + u];
         }
       }
       float ls = 0.0f;
@@ -657,12 +744,12 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
         if (c < C) {
           float w = 0.0f;
           if (cnt > 0) {
-            const float r = f[c] - mean[c] * icnt;
+            const float r = fr[(int64_t)c * V + v] - mean[c] * icnt;
             const float ar = fabsf(r);
             ls += ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta);
             w = (ar <= delta ? r : copysignf(delta, r)) * icnt;
           }
-          A.wsp[g.w_off + (int64_t)c * V + v] = w;
+          w_out[(int64_t)c * V + v] = w;
         }
       lsum += (double)ls;
     }
@@ -935,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_rprop(float* p, const float* g, float* 
 // ---------------------------------------------------------------------------
 static size_t pass_lds_bytes(int maxN, int n_split, int nacc_, int vpl) {
   const int rows = 4 / n_split;
-  size_t b = (size_t)maxN * 3 * sizeof(float4) + (size_t)8 * maxN * sizeof(float);
+  size_t b = (PRISM_ACQ_SMEM ? 0 : (size_t)maxN * 3 * sizeof(float4)) + (size_t)8 * maxN * sizeof(float);
   b += (size_t)rows * (n_split - 1) * nacc_ * 64 * vpl * sizeof(float);
   return b;
 }
@@ -947,7 +1034,8 @@ static hipError_t launch_pass_t(const PassArgs& a, hipStream_t s, int maxN) {
     hipLaunchKernelGGL((k_synth<K, LD>), dim3(a.n_items), dim3(kBlock),
                        (size_t)maxN * 3 * sizeof(float4), s, a);
   } else {
-    hipLaunchKernelGGL((k_pass<K, MODE, LD, VL>), dim3(a.n_items), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((k_pass<K, MODE, LD, VL>), dim3(a.n_items), dim3(kBlock), lds, s, a,
+                       reinterpret_cast<const float4*>(a.wsp));
   }
   return hipGetLastError();
 }
@@ -976,8 +1064,18 @@ hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int
   }
 }
 
+hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {
+  // only the scalar-cache variant of k_pass reads the global table
+  if (n_groups <= 0 || !PRISM_ACQ_SMEM) return hipSuccess;
+  hipLaunchKernelGGL(k_stage, dim3(n_groups), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fractions, dim3(n_items), dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_spatial, dim3(n_items), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
