@@ -122,3 +122,56 @@ def masked_group(shape, K, mode, seed, acq_kind="two96", bias="poly2", fill=0.7,
 
 def with_theta(g: I.Group, th: dict) -> I.Group:
     return dataclasses.replace(g, theta=th)
+
+
+# ----------------------------------------------------------------------------
+# full-size checks: the oracle in chunks on a spawned process pool
+# ----------------------------------------------------------------------------
+
+_FULL = {}
+
+
+def _full_workload(perturb_seed):
+    key = ("cfg2", perturb_seed)
+    if key not in _FULL:
+        w = I.config2()
+        g = w.groups[0]
+        if perturb_seed is not None:
+            g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(perturb_seed), scale=0.5))
+        _FULL.clear()
+        _FULL[key] = g
+    return _FULL[key]
+
+
+def oracle_chunk_cal(args):
+    """Data term and calibration gradient of one voxel chunk of the brain-shaped
+    volume (priors off; the calibration prior is added once by the caller)."""
+    perturb_seed, lo, hi = args
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+    g = _full_workload(perturb_seed)
+    prob = oracle_problem(g, norm_count=g.n_vox, coords=g.coords[lo:hi])
+    prob.priors = ()
+    th = theta32(g.theta)
+    th = {k: (v[..., lo:hi] if k not in ("bias", "alpha", "beta", "sigma_log") else v) for k, v in th.items()}
+    out, grad, _ = O.loss_grad(prob, th, np.asarray(g.y[:, lo:hi], np.float64))
+    return out["data"], grad["alpha"], grad["beta"], grad["bias"], float(grad["sigma_log"])
+
+
+def two_ring(coords, shape, centres):
+    """Indices of the voxels within two 6-neighbour steps of the centres."""
+    grid = -np.ones(shape, dtype=np.int64)
+    grid[tuple(coords.T)] = np.arange(coords.shape[0])
+    keep = set()
+    for c in centres:
+        for dx in range(-2, 3):
+            for dy in range(-2, 3):
+                for dz in range(-2, 3):
+                    if abs(dx) + abs(dy) + abs(dz) > 2:
+                        continue
+                    p = coords[c] + np.array([dx, dy, dz])
+                    if np.all(p >= 0) and np.all(p < np.array(shape)):
+                        v = grid[tuple(p)]
+                        if v >= 0:
+                            keep.add(int(v))
+    return np.array(sorted(keep))
