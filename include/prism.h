@@ -146,11 +146,14 @@ typedef struct {
 
 /* Launch shape of the fused pass (set by prism_problem_tune). */
 typedef struct {
-  int32_t vox_per_lane; /* 1 or 2 voxels per lane */
-  int32_t n_split;      /* 1, 2 or 4 waves sharing one voxel row (split over n) */
-  int32_t item_vox;     /* voxels per work item (one thread block), multiple of
-                           64 * vox_per_lane * 4 / n_split; 0 = automatic */
-  int32_t reserved;
+  int32_t vox_per_lane; /* 1 or 2 voxels per lane (the persistent launch uses 1) */
+  int32_t n_split;      /* 1, 2 or 4 waves sharing one voxel row (each over a part of
+                           the measurements); 0 = chosen per work item from its size */
+  int32_t item_vox;     /* voxels per work item (one thread block at a time), a
+                           multiple of 64 * vox_per_lane * 4 / n_split; 0 = automatic */
+  int32_t persistent;   /* 0: one launch per kernel variant (K, mode, learned D);
+                           1: one persistent launch over all work items, largest
+                           first, each block popping items from a device counter */
 } prism_launch;
 
 int32_t prism_abi_version(void);

@@ -69,7 +69,7 @@ class ProblemInfo(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("vox_per_lane", ctypes.c_int32), ("n_split", ctypes.c_int32),
-                ("item_vox", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("item_vox", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

@@ -49,6 +49,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Bucket {
   int K, mode, learn_d, maxN;
   int item_begin, item_count;
+  int xsplit;  // cross-wave buffer rows the launch needs
 };
 
 }  // namespace
@@ -65,6 +66,7 @@ struct prism_problem {
   std::vector<int32_t> tri_groups;
   std::vector<int32_t> acq_off;
   int max_field_chunks = 0;
+  int persistent_grid = 0;
   int64_t n_vox = 0, n_micro = 0, n_cal = 0, n_y = 0;
   size_t ws_rec = 0, ws_part = 0, ws_float = 0;  // element counts
   // device tables
@@ -105,63 +107,91 @@ namespace {
 
 int n_bias_of(int bias) { return bias == PRISM_BIAS_POLY2 ? 10 : bias == PRISM_BIAS_TRILINEAR8 ? 512 : 0; }
 
-// Work items, buckets and reduction tiles for the current launch shape.
+// Measurement split of one item: with n_split = 0 the item's size picks it
+// (few voxels -> more waves share each voxel row, each over a part of N).
+int item_split(const prism_launch& L, int nv) {
+  if (L.n_split > 0) return L.n_split;
+  const int lane_vox = 64 * L.vox_per_lane;
+  if (nv <= lane_vox) return 4;
+  if (nv <= 2 * lane_vox) return 2;
+  return 1;
+}
+
+int xsplit_of(int wn) { return (4 / wn) * (wn - 1); }  // cross-wave buffer rows
+
+// Work items, launch buckets and reduction tiles for the current launch shape.
 int plan(prism_problem* h) {
   const prism_launch& L = h->launch;
-  const int rows = 4 / L.n_split;
-  const int chunk = 64 * L.vox_per_lane * rows;
+  const int vpl = L.persistent ? 1 : L.vox_per_lane;
+  const int base_chunk = 64 * vpl * 4;  // voxels per block chunk with n_split = 1
   int item_vox = L.item_vox;
   if (item_vox <= 0) {
     // about six blocks per compute unit over the whole problem, whole chunks
     const int64_t target = 256 * 6;
     int64_t per = (h->n_vox + target - 1) / target;
-    per = ((per + chunk - 1) / chunk) * chunk;
-    item_vox = (int)std::max<int64_t>(chunk, std::min<int64_t>(per, 8 * chunk));
+    per = ((per + base_chunk - 1) / base_chunk) * base_chunk;
+    item_vox = (int)std::max<int64_t>(base_chunk, std::min<int64_t>(per, 8 * base_chunk));
   }
-  if (item_vox % chunk != 0)
-    return fail(PRISM_E_INVALID, "item_vox %d is not a multiple of the block chunk %d", item_vox, chunk);
+  if (L.n_split > 0 && item_vox % (64 * vpl * (4 / L.n_split)) != 0)
+    return fail(PRISM_E_INVALID, "item_vox %d is not a multiple of the block chunk %d", item_vox,
+                64 * vpl * (4 / L.n_split));
 
+  prism_launch Le = L;
+  Le.vox_per_lane = vpl;
   std::vector<ItemDev> items;
   std::vector<std::vector<int>> per_group(h->groups.size());
   for (size_t gi = 0; gi < h->groups.size(); ++gi) {
     GroupDev& g = h->groups[gi];
     int rec = 0;
     for (int v0 = 0; v0 < g.V; v0 += item_vox) {
-      ItemDev it;
+      ItemDev it{};
       it.group = (int)gi;
       it.v0 = v0;
       it.nv = std::min(item_vox, g.V - v0);
       it.rec = rec++;
+      it.n_split = item_split(Le, it.nv);
+      it.kind = ((g.K - 1) * 2 + g.mode) * 2 + g.learn_d;
       per_group[gi].push_back((int)items.size());
       items.push_back(it);
     }
     g.item_count = rec;
   }
-  // buckets by kernel variant; items inside a bucket largest-first (LPT)
+  auto cost = [&](const ItemDev& a) { return (int64_t)a.nv * h->groups[a.group].N * (h->groups[a.group].K + 2); };
   std::vector<Bucket> buckets;
   std::vector<ItemDev> ordered;
   ordered.reserve(items.size());
-  std::vector<bool> done(h->groups.size(), false);
-  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
-    if (done[gi]) continue;
-    const GroupDev& g0 = h->groups[gi];
-    Bucket b{g0.K, g0.mode, g0.learn_d, 0, (int)ordered.size(), 0};
-    std::vector<ItemDev> bi;
-    for (size_t gj = gi; gj < h->groups.size(); ++gj) {
-      const GroupDev& g = h->groups[gj];
-      if (done[gj] || g.K != b.K || g.mode != b.mode || g.learn_d != b.learn_d) continue;
-      done[gj] = true;
-      b.maxN = std::max(b.maxN, g.N);
-      for (int ii : per_group[gj]) bi.push_back(items[ii]);
+  if (L.persistent) {
+    // one launch; items largest first (LPT)
+    ordered = items;
+    std::stable_sort(ordered.begin(), ordered.end(),
+                     [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
+    Bucket b{0, 0, 0, 0, 0, (int)ordered.size(), 0};
+    for (const ItemDev& it : ordered) {
+      b.maxN = std::max(b.maxN, h->groups[it.group].N);
+      b.xsplit = std::max(b.xsplit, xsplit_of(it.n_split));
     }
-    std::stable_sort(bi.begin(), bi.end(), [&](const ItemDev& a, const ItemDev& c) {
-      const int64_t ca = (int64_t)a.nv * h->groups[a.group].N;
-      const int64_t cc = (int64_t)c.nv * h->groups[c.group].N;
-      return ca > cc;
-    });
-    ordered.insert(ordered.end(), bi.begin(), bi.end());
-    b.item_count = (int)bi.size();
     if (b.item_count > 0) buckets.push_back(b);
+  } else {
+    // one launch per kernel variant; items inside a bucket largest first (LPT)
+    std::vector<bool> done(h->groups.size(), false);
+    for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+      if (done[gi]) continue;
+      const GroupDev& g0 = h->groups[gi];
+      Bucket b{g0.K, g0.mode, g0.learn_d, 0, (int)ordered.size(), 0, 0};
+      std::vector<ItemDev> bi;
+      for (size_t gj = gi; gj < h->groups.size(); ++gj) {
+        const GroupDev& g = h->groups[gj];
+        if (done[gj] || g.K != b.K || g.mode != b.mode || g.learn_d != b.learn_d) continue;
+        done[gj] = true;
+        b.maxN = std::max(b.maxN, g.N);
+        for (int ii : per_group[gj]) bi.push_back(items[ii]);
+      }
+      std::stable_sort(bi.begin(), bi.end(), [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
+      for (const ItemDev& it : bi) b.xsplit = std::max(b.xsplit, xsplit_of(it.n_split));
+      ordered.insert(ordered.end(), bi.begin(), bi.end());
+      b.item_count = (int)bi.size();
+      if (b.item_count > 0) buckets.push_back(b);
+    }
   }
   // records and first-stage reduction tiles
   std::vector<TileDev> tiles;
@@ -195,6 +225,14 @@ int plan(prism_problem* h) {
   h->max_field_chunks = max_fc;
   h->ws_rec = (size_t)rec_off;
   h->ws_part = tiles.size() * 64;
+  h->persistent_grid = 0;
+  if (L.persistent && !buckets.empty()) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    const int bpc = persistent_blocks_per_cu(buckets[0].maxN, buckets[0].xsplit);
+    h->persistent_grid = std::max(1, std::min((int)ordered.size(), cus * bpc));
+  }
   hipError_t e = upload(&h->d_items, h->items);
   if (e == hipSuccess) e = upload(&h->d_tiles, h->tiles);
   if (e == hipSuccess) {
@@ -209,8 +247,10 @@ int plan(prism_problem* h) {
 int check_launch(const prism_launch* L) {
   if (L->vox_per_lane != 1 && L->vox_per_lane != 2)
     return fail(PRISM_E_INVALID, "vox_per_lane must be 1 or 2 (got %d)", L->vox_per_lane);
-  if (L->n_split != 1 && L->n_split != 2 && L->n_split != 4)
-    return fail(PRISM_E_INVALID, "n_split must be 1, 2 or 4 (got %d)", L->n_split);
+  if (L->n_split != 0 && L->n_split != 1 && L->n_split != 2 && L->n_split != 4)
+    return fail(PRISM_E_INVALID, "n_split must be 0 (per item), 1, 2 or 4 (got %d)", L->n_split);
+  if (L->persistent != 0 && L->persistent != 1)
+    return fail(PRISM_E_INVALID, "persistent must be 0 or 1");
   if (L->item_vox < 0) return fail(PRISM_E_INVALID, "item_vox must be >= 0");
   return PRISM_OK;
 }
@@ -396,7 +436,9 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   // default launch shape: split measurements across waves for small problems
   h->launch.vox_per_lane = vox >= 262144 ? 2 : 1;
   h->launch.n_split = vox < 65536 ? 4 : (vox < 262144 ? 2 : 1);
+  if (n_groups > 64) h->launch.n_split = 0;  // many groups: split per item size
   h->launch.item_vox = 0;
+  h->launch.persistent = 0;
   hipError_t e = upload(&h->d_bval, bval);
   if (e == hipSuccess) e = upload(&h->d_bvec, bvec);
   if (e == hipSuccess) e = upload(&h->d_coords, coords);
@@ -473,7 +515,7 @@ int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch) {
 int32_t prism_workspace_bytes(const prism_problem* h, size_t* bytes) {
   if (!h || !bytes) return fail(PRISM_E_INVALID, "NULL argument");
   *bytes = align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)) +
-           align256(h->ws_float * sizeof(float));
+           align256(h->ws_float * sizeof(float)) + 256;  // + the persistent launch's item counter
   return PRISM_OK;
 }
 
@@ -507,11 +549,23 @@ int32_t prism_synthesize(const prism_problem* h, const float* theta_micro, const
   PassArgs a = pass_args(h, nullptr, theta_micro, theta_cal, nullptr, nullptr, nullptr, nullptr);
   a.synth_only = 1;
   a.yhat = yhat;
-  for (const Bucket& b : h->buckets) {
-    a.item_base = b.item_begin;
-    a.n_items = b.item_count;
-    hipError_t e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, 1, b.maxN, s);
+  // one synthesis launch per item of the plan's variant groups (the synthesis
+  // kernel has no persistent form: it runs item by item per variant)
+  for (size_t i = 0; i < h->items.size();) {
+    const GroupDev& g0 = h->groups[h->items[i].group];
+    size_t j = i;
+    int maxN = 0;
+    while (j < h->items.size()) {
+      const GroupDev& g = h->groups[h->items[j].group];
+      if (g.K != g0.K || g.learn_d != g0.learn_d) break;
+      maxN = std::max(maxN, g.N);
+      ++j;
+    }
+    a.item_base = (int)i;
+    a.n_items = (int)(j - i);
+    hipError_t e = launch_pass_maxn(a, g0.K, g0.mode, g0.learn_d, 1, maxN, s);
     if (e != hipSuccess) return hip_fail(e, "synthesis launch");
+    i = j;
   }
   return PRISM_OK;
 }
@@ -533,6 +587,8 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
   double* rec = (double*)ws;
   double* part = (double*)(ws + align256(h->ws_rec * sizeof(double)));
   float* wsp = (float*)(ws + align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)));
+  int32_t* counter = (int32_t*)(ws + align256(h->ws_rec * sizeof(double)) +
+                                align256(h->ws_part * sizeof(double)) + align256(h->ws_float * sizeof(float)));
   PassArgs a = pass_args(h, y, theta_micro, theta_cal, grad_micro, rec, wsp, status);
   hipError_t e = launch_stage(a, (int)h->groups.size(), s);
   if (e != hipSuccess) return hip_fail(e, "acquisition staging launch");
@@ -545,9 +601,13 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
   for (const Bucket& b : h->buckets) {
     a.item_base = b.item_begin;
     a.n_items = b.item_count;
+    a.n_split = b.xsplit;
     const bool timed = h->prof && h->ev_used + 2 <= (int)h->ev.size();
     if (timed) (void)hipEventRecord(h->ev[h->ev_used], s);
-    e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, h->launch.vox_per_lane, b.maxN, s);
+    if (h->launch.persistent)
+      e = launch_pass_persistent(a, b.maxN, h->persistent_grid, counter, s);
+    else
+      e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, h->launch.vox_per_lane, b.maxN, s);
     if (e != hipSuccess) return hip_fail(e, "fused-pass launch");
     if (timed) {
       (void)hipEventRecord(h->ev[h->ev_used + 1], s);

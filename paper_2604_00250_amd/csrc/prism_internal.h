@@ -47,9 +47,11 @@ struct GroupDev {
 
 struct ItemDev {
   int32_t group;
-  int32_t v0;   // first voxel (group-local)
-  int32_t nv;   // voxels
-  int32_t rec;  // record index within the group
+  int32_t v0;       // first voxel (group-local)
+  int32_t nv;       // voxels
+  int32_t rec;      // record index within the group
+  int32_t n_split;  // waves sharing one voxel row of the block (1, 2 or 4)
+  int32_t kind;     // kernel variant ((K-1)*2 + mode)*2 + learned-D, for the persistent launch
 };
 
 // first-stage reduction tile: records [r0, r0+nr) of one group, fields [f0, f0+nf)
@@ -80,7 +82,7 @@ struct PassArgs {
   ModelDev model;
   int32_t item_base;       // first item of this launch
   int32_t n_items;         // items in this launch
-  int32_t n_split;         // waves sharing a voxel row
+  int32_t n_split;         // cross-wave buffer rows of the launch (max over items of rows*(WN-1))
   int32_t synth_only;      // forward model only (yhat written to g_micro as float [N][V])
   float* yhat;
 };
@@ -105,6 +107,9 @@ struct ReduceArgs {
 // launchers (prism_kernels.hip)
 hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s);
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
+hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
+                                  hipStream_t s);
+int persistent_blocks_per_cu(int maxN, int xsplit);
 hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
                             hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int max_tile_fields, hipStream_t s);

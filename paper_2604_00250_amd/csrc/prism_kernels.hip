@@ -24,6 +24,9 @@ namespace prism {
 #ifndef PRISM_TILE
 #define PRISM_TILE 16
 #endif
+#ifndef PRISM_PERSISTENT_MIN_WAVES
+#define PRISM_PERSISTENT_MIN_WAVES 2
+#endif
 #ifndef PRISM_ACQ_SMEM
 #define PRISM_ACQ_SMEM 0
 #endif
@@ -373,18 +376,27 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
   }
 }
 
+// statically sized LDS of the fused pass (one instance per kernel, shared by the
+// variants a persistent kernel inlines)
+struct PassShared {
+  double red[4][16];
+  double ep_d[2][kBlock];   // per-thread repulsion / sparsity partials
+  float ep_b[10][kBlock];   // per-thread quadratic-bias adjoint partials
+};
+
+// The fused pass over one work item (a run of one group's voxels).
 template <int K, int MODE, bool LD, int VL>
-__global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
-    PassArgs A, const float4* __restrict__ acq_global) {
-  extern __shared__ float4 smem4[];
-  __shared__ double red[4][16];
+__device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __restrict__ acq_global,
+                                          const ItemDev& it, float4* smem4, PassShared& sh) {
+  auto& red = sh.red;
+  auto& ep_d = sh.ep_d;
+  auto& ep_b = sh.ep_b;
   constexpr int C = K + 3;
   constexpr int NACC = Acc<K, LD>::N;
-  const ItemDev it = A.items[A.item_base + blockIdx.x];
   const GroupDev g = A.groups[it.group];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
-  const int WN = A.n_split, rows = 4 / WN;
+  const int WN = it.n_split, rows = 4 / WN;
   const int row = wave / WN, split = wave - row * WN;
   const int N = g.N;
   float4* acq = smem4;                                       // [3N] unless read from SMEM
@@ -412,8 +424,6 @@ __global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
   double dloss = 0.0, dsig = 0.0;
   // per-thread partials of the epilogue (repulsion, sparsity, quadratic-bias adjoint),
   // parked in LDS so that they are not live across the measurement loop
-  __shared__ double ep_d[2][kBlock];
-  __shared__ float ep_b[10][kBlock];
   ep_d[0][tid] = 0.0;
   ep_d[1][tid] = 0.0;
 #pragma unroll
@@ -624,6 +634,60 @@ __global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
     rec[kRecAlpha + N + n] = (double)accab[N + n] + (double)accab[3 * N + n] +
                              (double)accab[5 * N + n] + (double)accab[7 * N + n];
   }
+}
+
+// One block per item of one kernel variant.
+template <int K, int MODE, bool LD, int VL>
+__global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
+    PassArgs A, const float4* __restrict__ acq_global) {
+  extern __shared__ float4 smem4[];
+  __shared__ PassShared sh;
+  const ItemDev it = A.items[A.item_base + blockIdx.x];
+  pass_item<K, MODE, LD, VL>(A, acq_global, it, smem4, sh);
+}
+
+// Persistent launch over items of every variant: each block pops the next item
+// (largest first) from a device counter and runs that item's variant.  Every
+// block leaves the loop once the counter passes the last item.
+__device__ __forceinline__ int item_kind(int K, int mode, int ld) { return ((K - 1) * 2 + mode) * 2 + ld; }
+
+template <int K>
+__device__ __forceinline__ void dispatch_item(const PassArgs& A, const float4* __restrict__ acq_global,
+                                              const ItemDev& it, float4* smem4, PassShared& sh) {
+  switch (it.kind & 3) {
+    case 0: pass_item<K, kMSE, false, 1>(A, acq_global, it, smem4, sh); break;
+    case 1: pass_item<K, kMSE, true, 1>(A, acq_global, it, smem4, sh); break;
+    case 2: pass_item<K, kNLL, false, 1>(A, acq_global, it, smem4, sh); break;
+    default: pass_item<K, kNLL, true, 1>(A, acq_global, it, smem4, sh); break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock, PRISM_PERSISTENT_MIN_WAVES) void k_pass_persistent(PassArgs A,
+                                                            const float4* __restrict__ acq_global,
+                                                            int32_t* counter) {
+  extern __shared__ float4 smem4[];
+  __shared__ PassShared sh;
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();  // the previous item's LDS reads are done
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int i = next;
+    if (i >= A.n_items) break;
+    const ItemDev it = A.items[A.item_base + i];
+    switch ((it.kind >> 2) + 1) {
+      case 1: dispatch_item<1>(A, acq_global, it, smem4, sh); break;
+      case 2: dispatch_item<2>(A, acq_global, it, smem4, sh); break;
+      case 3: dispatch_item<3>(A, acq_global, it, smem4, sh); break;
+      case 4: dispatch_item<4>(A, acq_global, it, smem4, sh); break;
+      case 5: dispatch_item<5>(A, acq_global, it, smem4, sh); break;
+      default: dispatch_item<6>(A, acq_global, it, smem4, sh); break;
+    }
+  }
+}
+
+__global__ void k_counter_reset(int32_t* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1020,16 +1084,22 @@ __global__ __launch_bounds__(256) void k_rprop(float* p, const float* g, float* 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static size_t pass_lds_bytes(int maxN, int n_split, int nacc_, int vpl) {
-  const int rows = 4 / n_split;
+// dynamic LDS: acquisition table, per-wave measurement sums and the cross-wave
+// buffer of the worst measurement split in the launch (xsplit = max rows*(WN-1): 0, 2 or 3)
+static size_t pass_lds_bytes(int maxN, int xsplit, int nacc_, int vpl) {
   size_t b = (PRISM_ACQ_SMEM ? 0 : (size_t)maxN * 3 * sizeof(float4)) + (size_t)8 * maxN * sizeof(float);
-  b += (size_t)rows * (n_split - 1) * nacc_ * 64 * vpl * sizeof(float);
+  b += (size_t)xsplit * nacc_ * 64 * vpl * sizeof(float);
   return b;
 }
 
 template <int K, int MODE, bool LD, int VL>
 static hipError_t launch_pass_t(const PassArgs& a, hipStream_t s, int maxN) {
   const size_t lds = pass_lds_bytes(maxN, a.n_split, (K + 3) + 3 * K + 2 + (LD ? 2 : 0), VL);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pass<K, MODE, LD, VL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   if (a.synth_only) {
     hipLaunchKernelGGL((k_synth<K, LD>), dim3(a.n_items), dim3(kBlock),
                        (size_t)maxN * 3 * sizeof(float4), s, a);
@@ -1062,6 +1132,30 @@ hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int
     case 6: return dispatch_mode<6>(a, mode, learn_d, vpl, s, maxN);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
+                                  hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  const size_t lds = pass_lds_bytes(maxN, a.n_split, (kMaxK + 3) + 3 * kMaxK + 4, 1);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pass_persistent,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, s, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pass_persistent, dim3(grid), dim3(kBlock), lds, s, a,
+                     reinterpret_cast<const float4*>(a.wsp), counter);
+  return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int maxN, int xsplit) {
+  const size_t lds = pass_lds_bytes(maxN, xsplit, (kMaxK + 3) + 3 * kMaxK + 4, 1);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_persistent, kBlock, lds) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {

@@ -83,13 +83,15 @@ class Problem:
         except Exception:
             pass
 
-    def tune(self, vox_per_lane=1, n_split=1, item_vox=0):
-        L.check(L.lib().prism_problem_tune(self.handle, ctypes.byref(L.Launch(vox_per_lane, n_split, item_vox, 0))))
+    def tune(self, vox_per_lane=1, n_split=1, item_vox=0, persistent=0):
+        L.check(L.lib().prism_problem_tune(self.handle, ctypes.byref(
+            L.Launch(vox_per_lane, n_split, item_vox, int(persistent)))))
 
     def launch(self) -> dict:
         ln = L.Launch()
         L.check(L.lib().prism_problem_launch(self.handle, ctypes.byref(ln)))
-        return dict(vox_per_lane=ln.vox_per_lane, n_split=ln.n_split, item_vox=ln.item_vox)
+        return dict(vox_per_lane=ln.vox_per_lane, n_split=ln.n_split, item_vox=ln.item_vox,
+                    persistent=ln.persistent)
 
     def workspace_bytes(self) -> int:
         n = ctypes.c_size_t()
@@ -217,6 +219,13 @@ class DeviceState:
             self.set_y(ys)
         if thetas is not None:
             self.set_params(thetas)
+
+    def resize_workspace(self):
+        """Re-size the workspace after the problem's launch plan changed."""
+        need = self.prob.workspace_bytes()
+        if need > self.ws.numel():
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        self.ws_bytes = need
 
     def _s(self):
         st = self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
