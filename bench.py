@@ -209,6 +209,80 @@ def cpu_baseline(g, target_s=10.0, chunk=4096):
 # main
 # ----------------------------------------------------------------------------
 
+def stored_traffic(workload: str):
+    """HBM bytes per k_pass dispatch from the committed counter summary, if it
+    was taken with the current kernel sources (else None)."""
+    import re
+    from paper_2604_00250_amd.profile_summary import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", f"k_pass_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_dispatch: ([0-9.e+]+)", text)
+    h = re.search(r"kernel_source_sha1: ([0-9a-f]+)", text)
+    if not m or not h or h.group(1) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def parse_launch(text):
+    if not text:
+        return None
+    vals = [int(x) for x in text.split(",")]
+    keys = ("vox_per_lane", "n_split", "item_vox", "persistent")
+    return dict(zip(keys, vals))
+
+
+def bench_batched(args):
+    """4096 independent patches of uneven size (edge log-uniform 4-24), N in
+    {33, 96, 288}, K in 1..5, MSE or NLL, in one problem; the launch shape comes
+    from the autotuner (persistent or per-variant launches)."""
+    import numpy as np
+    import torch
+    from paper_2604_00250_amd import inputs as I
+    from paper_2604_00250_amd.problem import DeviceState, Problem
+    from paper_2604_00250_amd.tune import autotune
+    t0 = time.time()
+    w = I.config3()
+    log(f"workload {w.name}: {len(w.groups)} patches, {w.n_vox} voxels, generated in {time.time() - t0:.1f} s")
+    prob = Problem(w.groups)
+    st = DeviceState(prob, ys=[g.y for g in w.groups], thetas=[g.theta for g in w.groups], device="cuda:0")
+    launch = parse_launch(args.launch)
+    if launch:
+        prob.tune(**launch)
+        st.resize_workspace()
+        tuned = dict(launch=launch, cached=False)
+    else:
+        tuned = autotune(st, cache=None, reps=3)
+        log(f"autotuner: {tuned['launch']} ({tuned['ms']:.3f} ms); "
+            + "; ".join(f"{t['launch']}: {t['ms']:.3f}" for t in tuned["trials"]))
+    for _ in range(args.warmup):
+        st.iteration(lr=w.lr)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        st.iteration(lr=w.lr)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    V = w.n_vox
+    pairs = sum(g.n_vox * g.acq.n for g in w.groups)
+    out = {
+        "metric": METRIC, "value": V / (ms * 1e-3), "unit": "voxel-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "patches": len(w.groups), "voxels": V, "pairs": pairs,
+                   "launch": prob.launch(), "step": "prism_loss_grad + prism_adam_step"},
+        "pairs_per_s": pairs / (ms * 1e-3),
+        "autotune": {k: tuned[k] for k in ("launch", "cached") if k in tuned} | (
+            {"trials": tuned["trials"]} if "trials" in tuned else {}),
+        "status": int(st.status.cpu().item()),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +291,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
     ap.add_argument("--no-microbench", action="store_true")
-    ap.add_argument("--launch", type=str, default="", help="vox_per_lane,n_split,item_vox")
+    ap.add_argument("--launch", type=str, default="", help="vox_per_lane,n_split,item_vox[,persistent]")
+    ap.add_argument("--workload", choices=("brain", "batched"), default="brain",
+                    help="brain: the 743k-voxel volume (the metric's configuration); batched: 4096 "
+                         "independent uneven patches in one problem, autotuned launch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures the single-GPU path only: this build runs the fused pass on one "
@@ -228,6 +305,8 @@ def main():
     import numpy as np
     from paper_2604_00250_amd import inputs as I
 
+    if args.workload == "batched":
+        return bench_batched(args)
     t0 = time.time()
     w = I.config2()
     g = w.groups[0]
@@ -239,10 +318,7 @@ def main():
 
     import torch
     from paper_2604_00250_amd.problem import DeviceState, Problem
-    launch = None
-    if args.launch:
-        vpl, ns, iv = (int(x) for x in args.launch.split(","))
-        launch = dict(vox_per_lane=vpl, n_split=ns, item_vox=iv)
+    launch = parse_launch(args.launch)
     prob = Problem([g], launch=launch)
     st = DeviceState(prob, ys=[g.y], thetas=[g.theta], device="cuda:0")
     V = g.n_vox
@@ -290,8 +366,10 @@ def main():
     q = mb["q_exp"] if mb else 1.0
     slots = pairs * (ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR)
     achieved = slots / (k_ms * 1e-3)
+    traffic = stored_traffic(w.name)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
-                    frac=achieved / PEAK_SLOTS, traffic=None,
+                    frac=achieved / PEAK_SLOTS, traffic=traffic,
+                    traffic_vs_algorithmic=(traffic / (ALG_BYTES_PER_VOXEL * V)) if traffic else None,
                     kernel="k_pass<3,MSE,fixedD>", kernel_ms=k_ms, launches=k_launches,
                     alg_slots_per_pair=ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR, q_exp=q,
                     hbm_GBps=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / 1e9,

@@ -29,3 +29,43 @@ def main(stats_csv, bench_json, out_md, command):
 
 if __name__ == "__main__":
     main(*sys.argv[1:5])
+
+
+def kernel_source_hash(root=None) -> str:
+    """SHA-1 of the kernel sources (a profile's counters describe this build only)."""
+    import hashlib
+    import os
+    here = root or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha1()
+    for name in ("prism_kernels.hip", "prism_device.h", "prism_internal.h", "bessel_fit.h"):
+        with open(os.path.join(here, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def traffic_summary(fetch_csv, write_csv, out_md, kernel, command_fetch, command_write, workload):
+    """FETCH_SIZE / WRITE_SIZE per dispatch of `kernel`, scaled by what the same
+    counters read for the microbenchmark's copy of a known size (2 x 1 GiB)."""
+    def per_kernel(path):
+        agg = {}
+        for r in csv.DictReader(open(path)):
+            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in agg.items()}
+    f = per_kernel(fetch_csv)
+    w = per_kernel(write_csv)
+    kib = 1 << 30 >> 10  # the copy reads 1 GiB and writes 1 GiB
+    sf = kib / f["mb_copy_kernel"]
+    sw = kib / w["mb_copy_kernel"]
+    fk, wk = f[kernel], w[kernel]
+    traffic = (fk * sf + wk * sw) * 1024
+    with open(out_md, "w") as o:
+        o.write(f"# HBM traffic of {kernel} on {workload}\n\n")
+        o.write("Two rocprofv3 counter passes of the benchmark (repository root `$R`):\n\n```\n"
+                + command_fetch + "\n" + command_write + "\n```\n\n")
+        o.write("| counter | mb_copy_kernel (KiB/dispatch, 1 GiB read + 1 GiB written) | scale | "
+                f"{kernel} (KiB/dispatch) | scaled bytes |\n|---|---|---|---|---|\n")
+        o.write(f"| FETCH_SIZE | {f['mb_copy_kernel']:.1f} | {sf:.4f} | {fk:.1f} | {fk * sf * 1024:.4e} |\n")
+        o.write(f"| WRITE_SIZE | {w['mb_copy_kernel']:.1f} | {sw:.4f} | {wk:.1f} | {wk * sw * 1024:.4e} |\n\n")
+        o.write(f"traffic_bytes_per_dispatch: {traffic:.6e}\n")
+        o.write(f"kernel_source_sha1: {kernel_source_hash()}\n")
+    return traffic
