@@ -15,8 +15,10 @@ What it computes (PRISM, arxiv 2604.00250), all in float64 with plain NumPy:
     B = exp(linear log-bias basis) (Sec. 2.3, item 1);
   * data terms: MSE, Eq. 8, and Rician NLL, Eq. 9, with sigma = exp(sigma_log);
   * priors (Sec. 2.4): local Huber-Laplacian on the fractions (Eq. 7),
-    direction repulsion, L1 sparsity of minor fibre fractions and L2
-    calibration penalties;
+    direction repulsion, L1 sparsity of minor fibre fractions, the three
+    stabilisation terms (orphan-WM suppression, directional continuity,
+    fibre ordering), L2 calibration penalties and total variation of the
+    bias field;
   * the exact gradient of the total objective (Sec. 2.5) with respect to
     every raw parameter, derived by hand (chain rule of Eq. 3-9);
   * Adam (Kingma & Ba, Algorithm 1, with PyTorch's conventions) and Rprop
@@ -30,6 +32,12 @@ like Eq. 7; the sparsity indicator 1[f_k < tau] is held constant in the
 derivative; the derivative of |u| at 0 is 0; the calibration L2 weights are
 0.01 each; sigma_log is not regularised; N(x) is the set of in-mask
 neighbours inside the problem and a voxel without neighbours contributes 0.
+The stabilisation terms have printed weights but no printed form; they are
+read as: orphan-WM = sum_x max(0, 1 - S0/s_o) sum_k f_wm,k with s_o = 0.1;
+continuity = sum_x 1/|N(x)| sum_{x' in N(x)} sum_k (1 - (d_k(x).d_k(x'))^2);
+ordering = sum_x sum_k max(0, f_wm,k+1 - f_wm,k); all three averaged over
+|M|.  Bias TV = (lam_tv/|M|) sum over in-mask face-neighbour pairs
+(x, x + e_a) of |B(x + e_a) - B(x)|, lam_tv = 0.01.
 
 The Bessel functions of Eq. 9 use scipy.special.i0e / i1e (exponentially
 scaled I0, I1) so that log I0(z) = |z| + log i0e(|z|) cannot overflow.
@@ -67,6 +75,13 @@ class Constants:
     lam_alpha: float = 0.01
     lam_beta: float = 0.01
     lam_bias: float = 0.01
+    # Sec. 2.4 stabilisation terms: weights printed, forms and the S0 level read
+    lam_orphan: float = 0.01
+    s0_orphan: float = 0.1
+    lam_cont: float = 0.005
+    lam_order: float = 0.01
+    # Sec. 2.4 total variation of the upsampled bias field: weight read as 0.01
+    lam_tv: float = 0.01
 
 
 @dataclasses.dataclass
@@ -371,11 +386,105 @@ def calibration_prior(th: dict, c: Constants):
     return float(loss), 2 * c.lam_alpha * a, 2 * c.lam_beta * b, 2 * c.lam_bias * w
 
 
+def orphan_prior(prob: Problem, S0, f, c: Constants):
+    """Orphan-WM suppression (Sec. 2.4): WM fractions are penalised where S0 is
+    near zero, read as (lam/|M|) sum_x h(S0(x)) sum_k f_wm,k(x) with the hinge
+    h(s) = max(0, 1 - s/s_o).  Returns the loss and dR/dS0, dR/df_wm."""
+    K = prob.K
+    fw_sum = f[2:2 + K].sum(0)
+    h = np.maximum(0.0, 1.0 - S0 / c.s0_orphan)
+    scale = c.lam_orphan / prob.M
+    loss = scale * float((h * fw_sum).sum())
+    g_S0 = np.where(S0 < c.s0_orphan, -(scale / c.s0_orphan) * fw_sum, 0.0)
+    g_f = scale * np.repeat(h[None], K, axis=0)
+    return loss, g_S0, g_f
+
+
+def continuity_prior(prob: Problem, d, c: Constants):
+    """Directional continuity (Sec. 2.4): fibre k of a voxel is pulled toward
+    fibre k of its neighbours, read as
+    (lam/|M|) sum_x 1/|N(x)| sum_{x' in N(x)} sum_k (1 - (d_k(x).d_k(x'))^2),
+    sign-free like the fibre model.  N(x) is the Eq. 7 neighbourhood.
+    Returns the loss and dR/dd (unit directions)."""
+    K = prob.K
+    scale = c.lam_cont / prob.M
+    gd = np.zeros_like(d)
+    nb = neighbour_table(prob)
+    if nb.shape[1] == 0:
+        return 0.0, gd
+    valid = nb >= 0
+    cnt = valid.sum(1)
+    a = np.where(cnt > 0, 1.0 / np.maximum(cnt, 1), 0.0)       # 1/|N(x)|
+    loss = 0.0
+    for j in range(nb.shape[1]):
+        x = np.nonzero(valid[:, j])[0]
+        u = nb[x, j]
+        for k in range(K):
+            dot = (d[k][:, x] * d[k][:, u]).sum(0)
+            loss += float((a[x] * (1.0 - dot * dot)).sum())
+            # the pair (x, u) appears in the sums of x and of u (N is symmetric)
+            gd[k][:, x] += (-2.0 * (a[x] + a[u]) * dot)[None] * d[k][:, u]
+    return scale * loss, scale * gd
+
+
+def ordering_prior(prob: Problem, f, c: Constants):
+    """Fibre ordering (Sec. 2.4): fibre slots are kept in descending order of
+    fraction, read as (lam/|M|) sum_x sum_k max(0, f_wm,k+1 - f_wm,k).
+    Returns the loss and dR/df_wm."""
+    K = prob.K
+    fw = f[2:2 + K]
+    scale = c.lam_order / prob.M
+    g = np.zeros_like(fw)
+    loss = 0.0
+    for k in range(K - 1):
+        gap = fw[k + 1] - fw[k]
+        on = gap > 0
+        loss += float(gap[on].sum())
+        g[k + 1] += on
+        g[k] -= on
+    return scale * loss, scale * g
+
+
+def face_neighbours(prob: Problem):
+    """nb [V, 6] in-mask face neighbours (-x, +x, -y, +y, -z, +z), -1 if absent."""
+    grid = -np.ones(prob.shape, dtype=np.int64)
+    cx, cy, cz = prob.coords.T
+    grid[cx, cy, cz] = np.arange(prob.V)
+    nb = -np.ones((prob.V, 6), dtype=np.int64)
+    for a in range(3):
+        for s, col in ((-1, 2 * a), (1, 2 * a + 1)):
+            p = [cx.copy(), cy.copy(), cz.copy()]
+            p[a] = p[a] + s
+            ok = (p[a] >= 0) & (p[a] < prob.shape[a])
+            nb[ok, col] = grid[p[0][ok], p[1][ok], p[2][ok]]
+    return nb
+
+
+def tv_prior(prob: Problem, logB, c: Constants):
+    """Total variation of the bias field (Sec. 2.4 calibration regularisers),
+    read as (lam_tv/|M|) sum over in-mask pairs (x, x + e_a) of
+    |B(x + e_a) - B(x)|, B = exp(log-bias).  Returns the loss and dR/dlogB."""
+    B = np.exp(logB)
+    nb = face_neighbours(prob)
+    scale = c.lam_tv / prob.M
+    g = np.zeros(prob.V)
+    loss = 0.0
+    for a in range(3):
+        x = np.nonzero(nb[:, 2 * a + 1] >= 0)[0]
+        u = nb[x, 2 * a + 1]
+        diff = B[u] - B[x]
+        loss += float(np.abs(diff).sum())
+        s = np.sign(diff)
+        np.add.at(g, u, s * B[u])          # d|B(u) - B(x)| / dlogB(u)
+        np.add.at(g, x, -s * B[x])         # d|B(u) - B(x)| / dlogB(x)
+    return scale * loss, scale * g
+
+
 # ----------------------------------------------------------------------------
 # objective and its gradient (Sec. 2.5: L_data + sum_i lam_i R_i + R_cal)
 # ----------------------------------------------------------------------------
 
-TERMS = ("data", "spatial", "rep", "sparse", "cal", "total")
+TERMS = ("data", "spatial", "rep", "sparse", "orphan", "continuity", "ordering", "cal", "tv", "total")
 
 
 def objective(prob: Problem, th: dict, y, c: Constants = Constants()):
@@ -389,8 +498,17 @@ def objective(prob: Problem, th: dict, y, c: Constants = Constants()):
         out["rep"] = repulsion_prior(prob, tr["f"], tr["d"], c)[0]
     if "sparse" in prob.priors:
         out["sparse"] = sparsity_prior(prob, tr["f"], c)[0]
+    if "orphan" in prob.priors:
+        out["orphan"] = orphan_prior(prob, tr["S0"], tr["f"], c)[0]
+    if "continuity" in prob.priors:
+        out["continuity"] = continuity_prior(prob, tr["d"], c)[0]
+    if "ordering" in prob.priors:
+        out["ordering"] = ordering_prior(prob, tr["f"], c)[0]
     if "cal" in prob.priors:
         out["cal"] = calibration_prior(th, c)[0]
+    if "tv" in prob.priors and prob.bias != "none":
+        Phi = bias_basis(prob)
+        out["tv"] = tv_prior(prob, Phi.T @ np.asarray(th["bias"], dtype=np.float64), c)[0]
     out["total"] = sum(out[k] for k in TERMS[:-1])
     return out
 
@@ -429,6 +547,10 @@ def loss_grad(prob: Problem, th: dict, y, c: Constants = Constants()):
     g_beta = gy.sum(1)
     g_alpha = (gy * q).sum(1)
     g_logB = (gy * q).sum(0)
+    if "tv" in prob.priors and prob.bias != "none":
+        l, gtv = tv_prior(prob, logB, c)
+        out["tv"] = l
+        g_logB = g_logB + gtv
     g_bias = Phi @ g_logB if Phi.shape[0] else np.zeros(0)
     gS = gy * AB                        # dL/dS [N, V]
     # tissue signal (Eq. 3)
@@ -471,6 +593,19 @@ def loss_grad(prob: Problem, th: dict, y, c: Constants = Constants()):
         l, gfs = sparsity_prior(prob, f, c)
         out["sparse"] = l
         g_f[2:2 + K] += gfs
+    if "orphan" in prob.priors:
+        l, gso, gfo = orphan_prior(prob, S0, f, c)
+        out["orphan"] = l
+        g_S0 = g_S0 + gso
+        g_f[2:2 + K] += gfo
+    if "continuity" in prob.priors:
+        l, gdc = continuity_prior(prob, d, c)
+        out["continuity"] = l
+        g_d = g_d + gdc
+    if "ordering" in prob.priors:
+        l, gfo = ordering_prior(prob, f, c)
+        out["ordering"] = l
+        g_f[2:2 + K] += gfo
     if "cal" in prob.priors:
         l, ga, gb, gw = calibration_prior(th, c)
         out["cal"] = l
