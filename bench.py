@@ -317,6 +317,7 @@ def main():
         log(f"cpu baseline: {cpu['value']:.4g} voxel-iters/s on {cpu['cores']} cores")
 
     import torch
+    from paper_2604_00250_amd import _lib as L
     from paper_2604_00250_amd.problem import DeviceState, Problem
     launch = parse_launch(args.launch)
     prob = Problem([g], launch=launch)
@@ -343,7 +344,7 @@ def main():
     k_ms = k_ms_total / max(k_launches, 1)
     status = int(st.status.cpu().item())
     loss = st.loss_host()[0]
-    if status != 0 or not np.isfinite(loss[5]):
+    if status != 0 or not np.isfinite(loss[L.LOSS_TOTAL]):
         log(f"WARNING: status {status}, loss {loss}")
 
     # fwd+adjoint only (prism_loss_grad), same state
@@ -393,7 +394,7 @@ def main():
         "fwd_adjoint": {"value": V / (ms_fa * 1e-3), "ms": ms_fa},
         "roofline": roofline,
         "wall_s_timed": t_wall,
-        "loss": float(loss[5]),
+        "loss": float(loss[L.LOSS_TOTAL]),
         "status": status,
         "paper_context": "~741k voxels x 100 iterations per slab in ~12 min on one RTX A6000 "
                          "(about 1e5 voxel-iters/s, MSE; a different machine and workload)",

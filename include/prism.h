@@ -13,7 +13,9 @@
  *                            with s = exp(sigma_log)
  *   priors        (Sec. 2.4) Huber-Laplacian on the fractions (Eq. 7),
  *                            direction repulsion, sparsity of minor fibres,
- *                            L2 on the calibration parameters
+ *                            orphan-WM suppression, directional continuity,
+ *                            fibre ordering, L2 on the calibration parameters
+ *                            and total variation of the bias field
  *
  * and the exact gradient of the total objective (Sec. 2.5) with respect to
  * every raw parameter.  Readings of points the paper leaves open are fixed in
@@ -35,7 +37,8 @@
  *   - y and yhat of a group: float32 [N][V] at its y_offset.
  *   - grad_micro / grad_cal mirror theta_micro / theta_cal.
  *   - loss: float64 [n_groups][PRISM_LOSS_TERMS] (data, spatial, rep,
- *     sparse, cal, total).
+ *     sparse, orphan, continuity, ordering, cal, tv, total); the total is at
+ *     index PRISM_LOSS_TOTAL.
  *   - Every tensor argument of a per-iteration call is a caller-owned DEVICE
  *     pointer that must stay valid until the work queued on `stream` (a
  *     hipStream_t passed as void*, NULL = the default stream) completes.
@@ -58,11 +61,12 @@
 extern "C" {
 #endif
 
-#define PRISM_ABI_VERSION 1
+#define PRISM_ABI_VERSION 2
 #define PRISM_MAX_K 6
 #define PRISM_MAX_MEAS 1024
 #define PRISM_MAX_EDGE 1023
-#define PRISM_LOSS_TERMS 6
+#define PRISM_LOSS_TERMS 10
+#define PRISM_LOSS_TOTAL 9
 
 typedef enum {
   PRISM_OK = 0,
@@ -75,8 +79,20 @@ typedef enum {
 
 enum { PRISM_MSE = 0, PRISM_RICIAN = 1 };                     /* Eq. 8, Eq. 9 */
 enum { PRISM_BIAS_NONE = 0, PRISM_BIAS_POLY2 = 1, PRISM_BIAS_TRILINEAR8 = 2 };
-enum {                                                         /* Sec. 2.4 */
-  PRISM_PRIOR_SPATIAL = 1, PRISM_PRIOR_REP = 2, PRISM_PRIOR_SPARSE = 4, PRISM_PRIOR_CAL = 8
+/* Priors (Sec. 2.4).  The paper prints the stabilisation terms' weights but
+ * not their forms; these are read as (sums over masked voxels x, averaged
+ * over |M|, f_k the WM fractions, d_k the unit fibre directions):
+ *   ORPHAN      max(0, 1 - S0(x)/s0_orphan) * sum_k f_k(x)
+ *   CONTINUITY  1/|N(x)| sum_{x' in N(x)} sum_k (1 - (d_k(x).d_k(x'))^2),
+ *               N(x) the group's Eq. 7 neighbourhood (nothing when it is 0)
+ *   ORDERING    sum_k max(0, f_k+1(x) - f_k(x))
+ *   TV          sum_a [x + e_a masked] |B(x + e_a) - B(x)| over the three
+ *               axes (Sec. 2.4 calibration regularisers; needs a bias basis)
+ * The derivative of a kink (|0|, a hinge at 0) is taken as 0. */
+enum {
+  PRISM_PRIOR_SPATIAL = 1, PRISM_PRIOR_REP = 2, PRISM_PRIOR_SPARSE = 4, PRISM_PRIOR_CAL = 8,
+  PRISM_PRIOR_ORPHAN = 16, PRISM_PRIOR_CONTINUITY = 32, PRISM_PRIOR_ORDERING = 64,
+  PRISM_PRIOR_TV = 128
 };
 enum {                       /* bits OR-ed into the device status word */
   PRISM_ST_NONFINITE_LOSS = 1,
@@ -112,12 +128,15 @@ typedef struct {
 /* Model constants.  prism_model_defaults() fills the paper's values:
  * D_csf 3.0, D_gm 0.9, D_res 0.2 (Eq. 4), D_par 1.7, D_perp 0.4 (Eq. 5),
  * lam_sp 0.01 with Huber delta 0.05 (Eq. 7), lam_rep 0.01, lam_sparse 0.02
- * with tau 0.15 (Sec. 2.4), and the calibration L2 weights 0.01 (not printed
- * in the paper; a reading). */
+ * with tau 0.15, lam_orphan 0.01, lam_cont 0.005, lam_order 0.01 (Sec. 2.4),
+ * and values the paper does not print (readings): the calibration L2 weights
+ * 0.01, lam_tv 0.01, and s0_orphan 0.1 (S0 below which WM is penalised, on
+ * b0-normalised signals).  All must be finite and >= 0; s0_orphan > 0. */
 typedef struct {
   float d_csf, d_gm, d_res, d_par, d_perp;
   float lam_sp, huber_delta, lam_rep, lam_sparse, tau_sparse;
   float lam_alpha, lam_beta, lam_bias;
+  float lam_orphan, s0_orphan, lam_cont, lam_order, lam_tv;
 } prism_model;
 
 typedef struct prism_problem prism_problem;

@@ -22,9 +22,11 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "UNSUPPORTED", -3: "HIP", -4: "WORKS
 
 MSE, RICIAN = 0, 1
 BIAS = {"none": 0, "poly2": 1, "trilinear8": 2}
-PRIOR_BITS = {"spatial": 1, "rep": 2, "sparse": 4, "cal": 8}
+PRIOR_BITS = {"spatial": 1, "rep": 2, "sparse": 4, "cal": 8, "orphan": 16, "continuity": 32,
+              "ordering": 64, "tv": 128}
 ST_NONFINITE_LOSS, ST_NONFINITE_GRAD, ST_ZERO_DIRECTION = 1, 2, 4
-LOSS_TERMS = ("data", "spatial", "rep", "sparse", "cal", "total")
+LOSS_TERMS = ("data", "spatial", "rep", "sparse", "orphan", "continuity", "ordering", "cal", "tv", "total")
+LOSS_TOTAL = 9
 MAX_K = 6
 MAX_MEAS = 1024
 
@@ -51,7 +53,8 @@ class GroupDesc(ctypes.Structure):
 class Model(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in (
         "d_csf", "d_gm", "d_res", "d_par", "d_perp", "lam_sp", "huber_delta", "lam_rep",
-        "lam_sparse", "tau_sparse", "lam_alpha", "lam_beta", "lam_bias")]
+        "lam_sparse", "tau_sparse", "lam_alpha", "lam_beta", "lam_bias", "lam_orphan", "s0_orphan",
+        "lam_cont", "lam_order", "lam_tv")]
 
 
 class GroupInfo(ctypes.Structure):

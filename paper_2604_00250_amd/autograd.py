@@ -12,6 +12,8 @@ from __future__ import annotations
 
 import torch
 
+from . import _lib as L
+
 
 class PrismLoss(torch.autograd.Function):
     @staticmethod
@@ -28,7 +30,7 @@ class PrismLoss(torch.autograd.Function):
                               gm + 4 * st.n_micro, st.ws.data_ptr(), st.ws_bytes, st.status.data_ptr(),
                               st._s())
         ctx.save_for_backward(grad)
-        return st.loss[:, 5].sum()
+        return st.loss[:, L.LOSS_TOTAL].sum()
 
     @staticmethod
     def backward(ctx, g_out):

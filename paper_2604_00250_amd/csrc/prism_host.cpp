@@ -77,6 +77,7 @@ struct prism_problem {
   float* d_bvec = nullptr;
   int32_t* d_coords = nullptr;
   int32_t* d_nbr = nullptr;
+  float* d_ninv = nullptr;
   int32_t* d_grid = nullptr;
   int32_t* d_tri = nullptr;
   // optional timing of the fused kernel
@@ -97,6 +98,7 @@ struct prism_problem {
     (void)hipFree(d_bvec);
     (void)hipFree(d_coords);
     (void)hipFree(d_nbr);
+    (void)hipFree(d_ninv);
     (void)hipFree(d_grid);
     (void)hipFree(d_tri);
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -278,6 +280,11 @@ void prism_model_defaults(prism_model* m) {
   m->lam_alpha = 0.01f;
   m->lam_beta = 0.01f;
   m->lam_bias = 0.01f;
+  m->lam_orphan = 0.01f;
+  m->s0_orphan = 0.1f;
+  m->lam_cont = 0.005f;
+  m->lam_order = 0.01f;
+  m->lam_tv = 0.01f;
 }
 
 int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups, int32_t n_groups,
@@ -289,9 +296,12 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   if (!model) return fail(PRISM_E_INVALID, "model is NULL");
   const float mv[] = {model->d_csf, model->d_gm, model->d_res, model->d_par, model->d_perp,
                       model->lam_sp, model->huber_delta, model->lam_rep, model->lam_sparse,
-                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias};
+                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias,
+                      model->lam_orphan, model->s0_orphan, model->lam_cont, model->lam_order,
+                      model->lam_tv};
   for (float x : mv)
     if (!std::isfinite(x) || x < 0.0f) return fail(PRISM_E_INVALID, "model constants must be finite and >= 0");
+  if (!(model->s0_orphan > 0.0f)) return fail(PRISM_E_INVALID, "s0_orphan must be > 0");
   // acquisitions
   std::vector<int32_t> acq_off(n_acq);
   std::vector<float> bval, bvec;
@@ -322,8 +332,11 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   (void)hipGetDevice(&h->device);
   h->model = ModelDev{model->d_csf, model->d_gm, model->d_res, model->d_par, model->d_perp,
                       model->lam_sp, model->huber_delta, model->lam_rep, model->lam_sparse,
-                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias};
+                      model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias,
+                      model->lam_orphan, model->s0_orphan, model->lam_cont, model->lam_order,
+                      model->lam_tv};
   std::vector<int32_t> coords, nbr, grid;
+  std::vector<float> ninv;
   int64_t micro = 0, cal = 0, y = 0, vox = 0, wfl = 0;
   for (int gi = 0; gi < n_groups; ++gi) {
     const prism_group_desc& d = groups[gi];
@@ -341,12 +354,15 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
     if (d.neighbourhood != 0 && d.neighbourhood != 6 && d.neighbourhood != 26)
       return bad("neighbourhood must be 0, 6 or 26");
     if (d.learn_diffusivity != 0 && d.learn_diffusivity != 1) return bad("learn_diffusivity must be 0 or 1");
-    if (d.priors & ~0xFu) return bad("unknown prior bits");
+    if (d.priors & ~0xFFu) return bad("unknown prior bits");
     const int64_t box = (int64_t)d.nx * d.ny * d.nz;
     if (box > (int64_t)1 << 31) return bad("box too large");
     // compaction in raster order
     std::vector<int32_t> idx;
-    const bool need_idx = d.neighbourhood != 0 || d.bias == PRISM_BIAS_TRILINEAR8;
+    // the bias TV needs the face neighbours even without an Eq. 7 neighbourhood
+    const int ntab = d.neighbourhood != 0 ? d.neighbourhood
+                     : ((d.priors & PRISM_PRIOR_TV) && d.bias != PRISM_BIAS_NONE ? 6 : 0);
+    const bool need_idx = ntab != 0 || d.bias == PRISM_BIAS_TRILINEAR8;
     if (need_idx) idx.assign((size_t)box, -1);
     int32_t V = 0;
     const size_t cbase = coords.size();
@@ -381,18 +397,22 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
     g.acq_off = acq_off[d.acq];
     g.rec_stride = kRecHead + 2 * g.N;
     g.invM = V > 0 ? 1.0f / (float)V : 0.0f;
+    g.ntab = ntab;
     g.nbr_off = (int64_t)nbr.size();
-    if (d.neighbourhood != 0) {
-      std::vector<int> off;
-      for (int a = -1; a <= 1; ++a)
-        for (int b = -1; b <= 1; ++b)
-          for (int c = -1; c <= 1; ++c) {
-            const int m = std::abs(a) + std::abs(b) + std::abs(c);
-            if (m == 0 || (d.neighbourhood == 6 && m != 1)) continue;
-            off.push_back(a);
-            off.push_back(b);
-            off.push_back(c);
-          }
+    g.ninv_off = (int64_t)ninv.size();
+    if (ntab != 0) {
+      // face neighbours first (-x, +x, -y, +y, -z, +z), then the other 20 of 26
+      std::vector<int> off = {-1, 0, 0, 1, 0, 0, 0, -1, 0, 0, 1, 0, 0, 0, -1, 0, 0, 1};
+      if (ntab == 26)
+        for (int a = -1; a <= 1; ++a)
+          for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+              const int m = std::abs(a) + std::abs(b) + std::abs(c);
+              if (m < 2) continue;
+              off.push_back(a);
+              off.push_back(b);
+              off.push_back(c);
+            }
       const int nq = (int)off.size() / 3;
       const size_t nb0 = nbr.size();
       nbr.resize(nb0 + (size_t)nq * V, -1);
@@ -404,6 +424,13 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
           if (a < 0 || b < 0 || c < 0 || a >= d.nx || b >= d.ny || c >= d.nz) continue;
           nbr[nb0 + (size_t)q * V + v] = idx[((size_t)a * d.ny + b) * d.nz + c];
         }
+      }
+      // 1/|N(x)| over the Eq. 7 neighbourhood
+      ninv.resize(ninv.size() + (size_t)V, 0.0f);
+      for (int32_t v = 0; v < V && d.neighbourhood != 0; ++v) {
+        int cnt = 0;
+        for (int q = 0; q < d.neighbourhood; ++q) cnt += nbr[nb0 + (size_t)q * V + v] >= 0;
+        ninv[g.ninv_off + v] = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
       }
     }
     g.grid_off = (int64_t)grid.size();
@@ -443,6 +470,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   if (e == hipSuccess) e = upload(&h->d_bvec, bvec);
   if (e == hipSuccess) e = upload(&h->d_coords, coords);
   if (e == hipSuccess) e = upload(&h->d_nbr, nbr);
+  if (e == hipSuccess) e = upload(&h->d_ninv, ninv);
   if (e == hipSuccess) e = upload(&h->d_grid, grid);
   if (e == hipSuccess) e = upload(&h->d_tri, h->tri_groups);
   if (e != hipSuccess) {
@@ -528,6 +556,7 @@ static PassArgs pass_args(const prism_problem* h, const float* y, const float* t
   a.bvec = h->d_bvec;
   a.coords = h->d_coords;
   a.nbr = h->d_nbr;
+  a.ninv = h->d_ninv;
   a.y = y;
   a.th_micro = tm;
   a.th_cal = tc;

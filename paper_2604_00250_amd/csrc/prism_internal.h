@@ -12,24 +12,32 @@ constexpr int kWave = 64;
 constexpr int kMaxK = 6;
 constexpr int kMaxC = kMaxK + 3;     // tissue compartments (csf, gm, wm_1..K, res)
 constexpr int kAcqStride = 12;       // floats per staged measurement
-constexpr int kRecHead = 15;         // record fields before alpha[N], beta[N]
+constexpr int kRecHead = 19;         // record fields before alpha[N], beta[N]
 // record field indices (float64)
 enum RecField : int {
   kRecData = 0,     // data-term partial: MSE sum r^2, NLL sum of the positive parts
   kRecSpatial = 1,  // Huber-Laplacian partial (written by k_spatial)
   kRecRep = 2,      // repulsion partial
   kRecSparse = 3,   // sparsity partial
-  kRecSigma = 4,    // NLL: sum of (r^2/s^2 + 2z(1-R)) (d/dsigma_log = 2N|M| - this)
-  kRecBias = 5,     // 10 slots: sum_x phi_j(x) dlogB(x)
+  kRecOrphan = 4,   // orphan-WM partial
+  kRecCont = 5,     // directional-continuity partial
+  kRecOrder = 6,    // fibre-ordering partial
+  kRecTV = 7,       // bias-field total-variation partial
+  kRecSigma = 8,    // NLL: sum of (r^2/s^2 + 2z(1-R)) (d/dsigma_log = 2N|M| - this)
+  kRecBias = 9,     // 10 slots: sum_x phi_j(x) dlogB(x)
   kRecAlpha = kRecHead
 };
+constexpr int kLossTerms = 10;       // data, spatial, rep, sparse, orphan, continuity,
+                                     // ordering, cal, tv, total
 
 struct GroupDev {
   int64_t micro_off;  // float offset of theta_micro / grad_micro
   int64_t cal_off;    // float offset of theta_cal / grad_cal
   int64_t y_off;      // float offset of y / yhat
   int64_t vox_off;    // offset into per-voxel tables (coords)
-  int64_t nbr_off;    // int32 offset of the neighbour table [nbh][V]
+  int64_t nbr_off;    // int32 offset of the neighbour table [ntab][V]; entries 0-5 are
+                      // the face neighbours -x, +x, -y, +y, -z, +z, then the rest of 26
+  int64_t ninv_off;   // float offset of 1/|N(x)| [V] (0 without neighbours)
   int64_t w_off;      // float offset of the spatial weights [C][V] in the workspace
   int64_t glb_off;    // float offset of per-voxel dL/dlogB [V] in the workspace (trilinear)
   int64_t rec_off;    // float64 offset of the group's first item record
@@ -37,6 +45,7 @@ struct GroupDev {
   int64_t acqtab_off; // float offset of the staged acquisition table [N][12] in the workspace
   int32_t V, N, K, C, P;
   int32_t mode, bias, n_bias, learn_d, nbh, priors;
+  int32_t ntab;       // neighbour-table entries (nbh, or 6 for the bias TV alone)
   int32_t nx, ny, nz;
   int32_t acq_off;    // offset of the group's measurements in the acquisition arrays
   int32_t rec_stride; // float64 fields per record
@@ -63,6 +72,7 @@ struct ModelDev {
   float d_csf, d_gm, d_res, d_par, d_perp;
   float lam_sp, huber_delta, lam_rep, lam_sparse, tau_sparse;
   float lam_alpha, lam_beta, lam_bias;
+  float lam_orphan, s0_orphan, lam_cont, lam_order, lam_tv;
 };
 
 struct PassArgs {
@@ -72,6 +82,7 @@ struct PassArgs {
   const float* bvec;
   const int32_t* coords;   // packed i | j << 10 | k << 20
   const int32_t* nbr;
+  const float* ninv;       // 1/|N(x)| per voxel
   const float* y;
   const float* th_micro;
   const float* th_cal;

@@ -40,7 +40,10 @@ constexpr int kPf = PRISM_PREFETCH;
 static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
 
 enum { kMSE = 0, kNLL = 1 };
-enum { kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8 };
+enum {
+  kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8,
+  kPriorOrphan = 16, kPriorCont = 32, kPriorOrder = 64, kPriorTV = 128
+};
 enum { kStNonfiniteLoss = 1, kStNonfiniteGrad = 2, kStZeroDir = 4 };
 
 // ---------------------------------------------------------------------------
@@ -378,9 +381,11 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 
 // statically sized LDS of the fused pass (one instance per kernel, shared by the
 // variants a persistent kernel inlines)
+constexpr int kRecVals = 18;  // per-thread record values of the fused pass
 struct PassShared {
-  double red[4][16];
+  double red[4][kRecVals];
   double ep_d[2][kBlock];   // per-thread repulsion / sparsity partials
+  float ep_f[4][kBlock];    // per-thread orphan / continuity / ordering / TV partials
   float ep_b[10][kBlock];   // per-thread quadratic-bias adjoint partials
 };
 
@@ -390,6 +395,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
                                           const ItemDev& it, float4* smem4, PassShared& sh) {
   auto& red = sh.red;
   auto& ep_d = sh.ep_d;
+  auto& ep_f = sh.ep_f;
   auto& ep_b = sh.ep_b;
   constexpr int C = K + 3;
   constexpr int NACC = Acc<K, LD>::N;
@@ -426,6 +432,8 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   // parked in LDS so that they are not live across the measurement loop
   ep_d[0][tid] = 0.0;
   ep_d[1][tid] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ep_f[q][tid] = 0.0f;
 #pragma unroll
   for (int q = 0; q < 10; ++q) ep_b[q][tid] = 0.0f;
   bool bad_grad = false, zero_dir = false;
@@ -560,6 +568,66 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           }
           ep_d[1][tid] += (double)ls;
         }
+        if (g.priors & kPriorOrphan) {
+          // WM fractions where S0 is near zero: hinge max(0, 1 - S0/s0) on S0
+          const float s0o = A.model.s0_orphan;
+          const float sc = A.model.lam_orphan * g.invM;
+          const float h = fmaxf(0.0f, 1.0f - D.S0 / s0o);
+          float wsum = 0.0f;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            wsum += D.f[2 + k];
+            gf[2 + k] = fmaf(sc, h, gf[2 + k]);
+          }
+          if (D.S0 < s0o) gS0 -= (sc / s0o) * wsum;
+          ep_f[0][tid] += h * wsum;
+        }
+        if (g.priors & kPriorOrder) {
+          // fibre slots in descending order of fraction: hinge on each adjacent pair
+          const float sc = A.model.lam_order * g.invM;
+          float lo = 0.0f;
+#pragma unroll
+          for (int k = 0; k + 1 < K; ++k) {
+            const float gap = D.f[3 + k] - D.f[2 + k];
+            if (gap > 0.0f) {
+              lo += gap;
+              gf[3 + k] += sc;
+              gf[2 + k] -= sc;
+            }
+          }
+          ep_f[2][tid] += lo;
+        }
+        if ((g.priors & kPriorCont) && g.nbh > 0) {
+          // slot-wise alignment with the neighbours' directions; the pair (x, u)
+          // enters the sums of x and of u, weighted 1/|N(x)| and 1/|N(u)|
+          const int32_t* nbr = A.nbr + g.nbr_off;
+          const float* ninv = A.ninv + g.ninv_off;
+          const float* th = A.th_micro + g.micro_off;
+          const float sc2 = -2.0f * A.model.lam_cont * g.invM;
+          const float ax = ninv[v];
+          float lc = 0.0f;
+          for (int q = 0; q < g.nbh; ++q) {
+            const int u = nbr[(int64_t)q * V + v];
+            if (u < 0) continue;
+            const float w = sc2 * (ax + ninv[u]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              const float ux = th[(int64_t)row_v(C, k, 0) * V + u];
+              const float uy = th[(int64_t)row_v(C, k, 1) * V + u];
+              const float uz = th[(int64_t)row_v(C, k, 2) * V + u];
+              const float n2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+              const float in = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+              const float dx = ux * in, dy = uy * in, dz = uz * in;
+              const float dot = x[j].d[k][0] * dx + x[j].d[k][1] * dy + x[j].d[k][2] * dz;
+              lc = fmaf(ax, fmaf(-dot, dot, 1.0f), lc);
+              const float wd = w * dot;
+              gd[k][0] = fmaf(wd, dx, gd[k][0]);
+              gd[k][1] = fmaf(wd, dy, gd[k][1]);
+              gd[k][2] = fmaf(wd, dz, gd[k][2]);
+            }
+          }
+          ep_f[1][tid] += lc;
+        }
         // softmax chain rule
         float gsum = 0.0f;
 #pragma unroll
@@ -587,7 +655,32 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           gm[(int64_t)p * V + v] = gout[p];
         }
         // bias-field adjoint dL/dlogB(x)
-        const float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
+        float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
+        if ((g.priors & kPriorTV) && g.bias != 0) {
+          // |B(x+e_a) - B(x)| over the in-mask face pairs: x owns the pair toward +e_a
+          // and takes the derivative of both pairs it belongs to
+          const int32_t* nbr = A.nbr + g.nbr_off;
+          const float* cal = A.th_cal + g.cal_off;
+          const int32_t pc = A.coords[g.vox_off + v];
+          const float lb0 = log_bias(g, cal, pc);
+          const float B0 = x[j].B;
+          float lt = 0.0f, gt = 0.0f;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int32_t step = 1 << (10 * a);
+            if (nbr[(int64_t)(2 * a + 1) * V + v] >= 0) {
+              const float dl = log_bias(g, cal, pc + step) - lb0;
+              lt = fmaf(B0, fabsf(expm1f(dl)), lt);
+              gt += dl > 0.0f ? -B0 : (dl < 0.0f ? B0 : 0.0f);
+            }
+            if (nbr[(int64_t)(2 * a) * V + v] >= 0) {
+              const float dl = lb0 - log_bias(g, cal, pc - step);
+              gt += dl > 0.0f ? B0 : (dl < 0.0f ? -B0 : 0.0f);
+            }
+          }
+          glb = fmaf(A.model.lam_tv * g.invM, gt, glb);
+          ep_f[3][tid] += lt;
+        }
         if (g.bias == 1) {
           const int32_t pc = A.coords[g.vox_off + v];
           const int i = pc & 1023, jj = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
@@ -607,25 +700,28 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
   // ---- item record: per-problem sums and per-measurement sums ----
   double* rec = A.rec + g.rec_off + (int64_t)it.rec * g.rec_stride;
-  double vals[14];
+  double vals[kRecVals];
   vals[0] = dloss;
   vals[1] = ep_d[0][tid];
   vals[2] = ep_d[1][tid];
-  vals[3] = dsig;
 #pragma unroll
-  for (int q = 0; q < 10; ++q) vals[4 + q] = (double)ep_b[q][tid];
+  for (int q = 0; q < 4; ++q) vals[3 + q] = (double)ep_f[q][tid];
+  vals[7] = dsig;
 #pragma unroll
-  for (int q = 0; q < 14; ++q) {
+  for (int q = 0; q < 10; ++q) vals[8 + q] = (double)ep_b[q][tid];
+#pragma unroll
+  for (int q = 0; q < kRecVals; ++q) {
     const double s = wave_sum_f64(vals[q]);
     if (lane == 0) red[wave][q] = s;
   }
   if (bad_grad) atomicOr(A.status, (uint32_t)kStNonfiniteGrad);
   if (zero_dir) atomicOr(A.status, (uint32_t)kStZeroDir);
   __syncthreads();
-  if (tid < 14) {
+  if (tid < kRecVals) {
     const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     const int field = tid == 0 ? kRecData : tid == 1 ? kRecRep : tid == 2 ? kRecSparse
-                      : tid == 3 ? kRecSigma : kRecBias + (tid - 4);
+                      : tid < 7 ? kRecOrphan + (tid - 3) : tid == 7 ? kRecSigma
+                      : kRecBias + (tid - 8);
     rec[field] = s;
   }
   for (int n = tid; n < N; n += kBlock) {
@@ -914,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
     if (!isfinite(out)) atomicOr(R.status, (uint32_t)kStNonfiniteGrad);
   }
   if (fc == 0 && f == 0) {
-    // loss terms from fields 0-4 of the LDS partials of this (first) field chunk
+    // loss terms from fields 0-7 of the LDS partials of this (first) field chunk
     auto part_sum = [&](int fld) { return part[0][fld] + part[1][fld] + part[2][fld] + part[3][fld]; };
     const double data = g.mode == kMSE
                             ? part_sum(kRecData) * (double)g.invM
@@ -923,6 +1019,10 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
     const double sp = part_sum(kRecSpatial) * (double)R.model.lam_sp * g.invM;
     const double rp = part_sum(kRecRep) * (double)R.model.lam_rep * g.invM;
     const double sa = part_sum(kRecSparse) * (double)R.model.lam_sparse * g.invM;
+    const double orp = part_sum(kRecOrphan) * (double)R.model.lam_orphan * g.invM;
+    const double cnt = part_sum(kRecCont) * (double)R.model.lam_cont * g.invM;
+    const double ord = part_sum(kRecOrder) * (double)R.model.lam_order * g.invM;
+    const double tv = part_sum(kRecTV) * (double)R.model.lam_tv * g.invM;
     double cl = 0.0;
     if (cal_on) {
       const double qa = calsq[0][0] + calsq[0][1] + calsq[0][2] + calsq[0][3];
@@ -931,14 +1031,18 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
       cl = (double)R.model.lam_alpha * qa + (double)R.model.lam_beta * qb +
            (double)R.model.lam_bias * qw;
     }
-    double* L = R.loss + (int64_t)gi * 6;
+    double* L = R.loss + (int64_t)gi * kLossTerms;
     L[0] = data;
     L[1] = sp;
     L[2] = rp;
     L[3] = sa;
-    L[4] = cl;
-    L[5] = data + sp + rp + sa + cl;
-    if (!isfinite(L[5])) atomicOr(R.status, (uint32_t)kStNonfiniteLoss);
+    L[4] = orp;
+    L[5] = cnt;
+    L[6] = ord;
+    L[7] = cl;
+    L[8] = tv;
+    L[9] = data + sp + rp + sa + orp + cnt + ord + cl + tv;
+    if (!isfinite(L[9])) atomicOr(R.status, (uint32_t)kStNonfiniteLoss);
   }
 }
 

@@ -7,7 +7,8 @@ on the device; checkpoint / resume of the optimiser state.
     hist = fit(state, iterations=100, graph=False)       # eager
 
 The host synchronises once, at the end.  `history` is a float64 device tensor
-[iterations][n_groups][6] (data, spatial, rep, sparse, cal, total) of the
+[iterations][n_groups][10] (data, spatial, rep, sparse, orphan, continuity,
+ordering, cal, tv, total; the layout of the library's loss rows) of the
 loss evaluated at the start of each iteration.
 """
 from __future__ import annotations
@@ -15,6 +16,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
+from . import _lib as L
 from .problem import DeviceState, rprop_step_ptr
 
 
@@ -31,7 +33,7 @@ class Loop:
         self.eps = eps
         self.rprop = rprop
         dev = state.device
-        self.hist = torch.zeros((max(history, 1), state.prob.n_groups, 6), dtype=torch.float64, device=dev)
+        self.hist = torch.zeros((max(history, 1), state.prob.n_groups, len(L.LOSS_TERMS)), dtype=torch.float64, device=dev)
         self.hist_len = max(history, 1)
         self.graph = None
         if optimizer == "rprop":

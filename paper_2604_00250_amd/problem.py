@@ -209,7 +209,7 @@ class DeviceState:
         self.m = torch.zeros(n, **f32)
         self.v = torch.zeros(n, **f32)
         self.y = torch.zeros(max(self.n_y, 1), **f32)
-        self.loss = torch.zeros((prob.n_groups, 6), dtype=torch.float64, device=self.device)
+        self.loss = torch.zeros((prob.n_groups, len(L.LOSS_TERMS)), dtype=torch.float64, device=self.device)
         self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.step = torch.zeros(2, dtype=torch.int32, device=self.device)
         self.ws_bytes = prob.workspace_bytes()

@@ -42,17 +42,26 @@ def theta32(th):
     return {k: np.asarray(np.asarray(v, dtype=np.float32), dtype=np.float64) for k, v in th.items()}
 
 
-def run_oracle(g: I.Group, th: dict):
+def run_oracle(g: I.Group, th: dict, consts: O.Constants = O.Constants()):
     prob = oracle_problem(g)
     y = np.asarray(g.y, dtype=np.float64)
-    out, grad, yhat = O.loss_grad(prob, theta32(th), y)
+    out, grad, yhat = O.loss_grad(prob, theta32(th), y, consts)
     return out, grad, yhat
 
 
-def run_gpu(groups, thetas, launch=None, repeat=1):
+def model_of(consts: O.Constants):
+    """The library's model constants with the oracle's values."""
+    from paper_2604_00250_amd import _lib as L
+    m = L.model_defaults()
+    for name, _ in L.Model._fields_:
+        setattr(m, name, float(getattr(consts, name)))
+    return m
+
+
+def run_gpu(groups, thetas, launch=None, repeat=1, consts: O.Constants = None):
     from paper_2604_00250_amd.problem import DeviceState, Problem
     import torch
-    prob = Problem(groups, launch=launch)
+    prob = Problem(groups, launch=launch, model=None if consts is None else model_of(consts))
     st = DeviceState(prob, ys=[g.y for g in groups], thetas=thetas)
     for _ in range(repeat):
         st.loss_grad()
@@ -85,11 +94,12 @@ def class_errors(g_gpu: dict, g_ref: dict):
 
 
 def assert_parity(name, loss_gpu_row, g_gpu, out_ref, g_ref, loss_rtol=LOSS_RTOL, grad_rtol=GRAD_RTOL):
-    terms = ("data", "spatial", "rep", "sparse", "cal", "total")
+    terms = O.TERMS
+    it = terms.index("total")
     tot_ref = out_ref["total"]
-    rel = abs(loss_gpu_row[5] - tot_ref) / max(abs(tot_ref), 1e-300)
+    rel = abs(loss_gpu_row[it] - tot_ref) / max(abs(tot_ref), 1e-300)
     errs = class_errors(g_gpu, g_ref)
-    say(f"[{name}] loss gpu={loss_gpu_row[5]:.10g} ref={tot_ref:.10g} rel={rel:.2e} "
+    say(f"[{name}] loss gpu={loss_gpu_row[it]:.10g} ref={tot_ref:.10g} rel={rel:.2e} "
         + " ".join(f"{k}={v:.1e}" for k, v in errs.items()))
     for i, t in enumerate(terms[:-1]):
         ref = out_ref[t]

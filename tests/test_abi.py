@@ -29,15 +29,36 @@ def test_library_loads_and_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"binding misses {n}"
-    assert lib.prism_abi_version() == 1
+    assert lib.prism_abi_version() == 2
 
 
 def test_model_defaults_are_the_papers_constants():
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
     m = L.model_defaults()
     for k in ("d_csf", "d_gm", "d_res", "d_par", "d_perp", "huber_delta", "lam_sp", "lam_rep",
-              "lam_sparse", "tau_sparse"):
+              "lam_sparse", "tau_sparse", "lam_orphan"):
         assert getattr(m, k) == pytest.approx(gold[k]["value"], rel=1e-7), k
+    assert m.lam_cont == pytest.approx(gold["lam_continuity"]["value"], rel=1e-7)
+    assert m.lam_order == pytest.approx(gold["lam_ordering"]["value"], rel=1e-7)
+
+
+def test_model_defaults_equal_the_oracles_constants():
+    """Every constant the library defaults to (printed or a reading) is the
+    value the oracle uses."""
+    import oracle as O
+    m = L.model_defaults()
+    c = O.Constants()
+    for name, _ in L.Model._fields_:
+        assert getattr(m, name) == pytest.approx(getattr(c, name), rel=1e-7), name
+
+
+def test_loss_layout_matches_the_oracle_terms():
+    import oracle as O
+    assert L.LOSS_TERMS == O.TERMS
+    assert L.LOSS_TERMS[L.LOSS_TOTAL] == "total"
+    hdr = open(os.path.join(ROOT, "include", "prism.h")).read()
+    assert f"#define PRISM_LOSS_TERMS {len(L.LOSS_TERMS)}" in hdr
+    assert f"#define PRISM_LOSS_TOTAL {L.LOSS_TOTAL}" in hdr
 
 
 def _acq(n=5, bad_norm=False, neg_b=False):
@@ -73,7 +94,7 @@ def _create(edit_group=None, edit_acq=None, n_groups=1, model=None):
     ({"K": 0}, "K must be"), ({"K": 7}, "K must be"), ({"mode": 2}, "data mode"),
     ({"bias": 3}, "bias"), ({"acq": 1}, "acquisition index"), ({"neighbourhood": 4}, "neighbourhood"),
     ({"nx": 0}, "box"), ({"nz": 1024}, "box"), ({"learn_diffusivity": 2}, "learn_diffusivity"),
-    ({"priors": 16}, "prior bits"),
+    ({"priors": 256}, "prior bits"),
 ])
 def test_create_rejects_bad_group(edit, needle):
     rc, msg = _create(edit_group=edit)
@@ -92,6 +113,10 @@ def test_create_rejects_bad_acquisition_and_counts():
     m.lam_sp = float("nan")
     rc, msg = _create(model=m)
     assert rc == L.PRISM_E_INVALID and "finite" in msg
+    m = L.model_defaults()
+    m.s0_orphan = 0.0
+    rc, msg = _create(model=m)
+    assert rc == L.PRISM_E_INVALID and "s0_orphan" in msg
     lib = L.lib()
     assert lib.prism_problem_create(None, None, 0, None, 0, None) == L.PRISM_E_INVALID
     n = np.zeros(1025, dtype=np.float32)

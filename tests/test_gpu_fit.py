@@ -83,7 +83,7 @@ def test_graph_replay_equals_eager_iterations_bitwise():
     assert torch.equal(st.params, p_eager)
     assert torch.equal(loop.hist, h_eager)
     # the loss history decreases over the first iterations
-    tot = h_eager[:, :, 5].sum(1).cpu().numpy()
+    tot = h_eager[:, :, 9].sum(1).cpu().numpy()
     say(f"[graph] loss history {tot}")
     assert tot[-1] < tot[0]
 
@@ -151,7 +151,7 @@ def test_short_adam_trajectory_matches_oracle():
         ref_hist.append(out["total"])
         for k in keys:
             th[k], m[k], v[k] = O.adam_step(th[k], gr[k], m[k], v[k], t)
-    gpu_hist = hist[:, 0, 5].cpu().numpy()
+    gpu_hist = hist[:, 0, 9].cpu().numpy()
     say(f"[trajectory] gpu {gpu_hist} ref {np.array(ref_hist)}")
     assert np.allclose(gpu_hist, ref_hist, rtol=1e-5)
     pm, pc = st.params_host()
@@ -168,7 +168,7 @@ def test_fit_reduces_loss_on_the_calibrated_patch():
     st = _state([g])
     hist = fit(st, 60, lr=1e-2, graph=True)
     torch.cuda.synchronize()
-    tot = hist[:, 0, 5].cpu().numpy()
+    tot = hist[:, 0, 9].cpu().numpy()
     say(f"[fit patch16] loss {tot[0]:.6g} -> {tot[-1]:.6g}")
     assert np.all(np.isfinite(tot)) and tot[-1] < tot[0]
     assert int(st.status.item()) == 0

@@ -52,6 +52,8 @@ def test_brain_volume_full_size(perturb_seed):
     cl, ga, gb, gw = O.calibration_prior(th, O.Constants())
     ref["cal"] = cl
     ref["total"] = sum(ref[k] for k in ("data", "spatial", "rep", "sparse", "cal"))
+    for k in O.TERMS:
+        ref.setdefault(k, 0.0)
     # GPU, the benchmark's launch plan
     prob = Problem([g])
     st = DeviceState(prob, ys=[g.y], thetas=[g.theta])
@@ -60,10 +62,10 @@ def test_brain_volume_full_size(perturb_seed):
     loss = st.loss_host()[0]
     gm, gc = st.grads_host()
     assert int(st.status.item()) == 0
-    H.say(f"[full] launch {prob.launch()} loss gpu {loss[5]:.10g} ref {ref['total']:.10g}")
-    for i, t in enumerate(("data", "spatial", "rep", "sparse", "cal")):
+    H.say(f"[full] launch {prob.launch()} loss gpu {loss[9]:.10g} ref {ref['total']:.10g}")
+    for i, t in enumerate(O.TERMS[:-1]):
         assert abs(loss[i] - ref[t]) <= 1e-5 * abs(ref["total"]) + 1e-12, (t, loss[i], ref[t])
-    assert abs(loss[5] - ref["total"]) <= 1e-5 * abs(ref["total"])
+    assert abs(loss[9] - ref["total"]) <= 1e-5 * abs(ref["total"])
     errs = H.class_errors(gc[0], dict(alpha=g_alpha + ga, beta=g_beta + gb, bias=g_bias + gw))
     H.say(f"[full] calibration gradient errors {errs}")
     assert max(errs.values()) <= 1e-4

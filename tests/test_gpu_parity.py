@@ -89,7 +89,7 @@ def test_empty_group_contributes_only_calibration_prior():
     out, _, _ = O.objective(O.Problem(coords=np.zeros((0, 3), dtype=int), shape=(4, 4, 4), bval=g0.acq.bval,
                                       bvec=g0.acq.bvec, K=2, mode="mse", bias="poly2"),
                             theta32(empty.theta), np.zeros((33, 0))), None, None
-    assert r["loss"][1][5] == pytest.approx(out["total"], rel=1e-6, abs=1e-12)
+    assert r["loss"][1][9] == pytest.approx(out["total"], rel=1e-6, abs=1e-12)
     assert r["loss"][1][0] == 0.0
     cal = theta32(empty.theta)
     assert np.allclose(r["gcal"][1]["alpha"], 0.02 * cal["alpha"], rtol=1e-5, atol=1e-9)
