@@ -22,7 +22,9 @@ What it computes (PRISM, arxiv 2604.00250), all in float64 with plain NumPy:
   * the exact gradient of the total objective (Sec. 2.5) with respect to
     every raw parameter, derived by hand (chain rule of Eq. 3-9);
   * Adam (Kingma & Ba, Algorithm 1, with PyTorch's conventions) and Rprop
-    (Riedmiller & Braun 1993, PyTorch's variant).
+    (Riedmiller & Braun 1993, PyTorch's variant);
+  * the whole-volume slab layout and the weighted stitching of per-slab
+    maps (Sec. 2.5), with the readings stated at each function.
 
 Readings where the paper is silent (each is listed with its reason in the
 design notes): f_intra is per voxel and shared by the K fibres; the MSE is
@@ -631,6 +633,121 @@ def loss_grad(prob: Problem, th: dict, y, c: Constants = Constants()):
     grad["beta"] = g_beta
     grad["sigma_log"] = np.array(g_sigma if prob.mode == "nll" else 0.0)
     return out, grad, yhat
+
+
+# ----------------------------------------------------------------------------
+# whole-volume slabs and their stitching (Sec. 2.5)
+# ----------------------------------------------------------------------------
+
+def slab_ranges(nz: int, thickness: int = 30, overlap: int = 5):
+    """(first slice, slices) of each slab along z.  Slabs start every
+    thickness - overlap slices until one reaches the end of the volume; the
+    last one stops at the volume's edge and may be thinner (reading: the paper
+    gives only the thickness and the overlap).  Needs thickness >= 2 overlap,
+    so that no slice lies in more than two slabs."""
+    if not (0 <= 2 * overlap <= thickness):
+        raise ValueError("need 0 <= 2 overlap <= thickness")
+    out = []
+    z = 0
+    while True:
+        out.append((z, min(thickness, nz - z)))
+        if z + thickness >= nz:
+            return out
+        z += thickness - overlap
+
+
+def slab_weights(z0, thickness):
+    """Blend weight of each slab at each of its slices (reading of the paper's
+    weighted averaging): a linear ramp across each overlap with a neighbouring
+    slab, (s + 1)/(o + 1) at the s-th slice counted from the slab's edge for an
+    overlap of o slices, and 1 elsewhere.  The two ramps over an overlap sum to
+    one at every slice."""
+    G = len(z0)
+    out = []
+    for g in range(G):
+        a, b = z0[g], z0[g] + thickness[g]
+        o_lo = max(0, z0[g - 1] + thickness[g - 1] - a) if g > 0 else 0
+        o_hi = max(0, b - z0[g + 1]) if g + 1 < G else 0
+        z = np.arange(a, b, dtype=np.float64)
+        w = np.ones(b - a)
+        if o_lo:
+            w = np.minimum(w, (z - a + 1.0) / (o_lo + 1.0))
+        if o_hi:
+            w = np.minimum(w, (b - z) / (o_hi + 1.0))
+        out.append(w)
+    return out
+
+
+def constrained_maps(prob: Problem, th: dict, c: Constants = Constants()):
+    """Per-voxel constrained quantities [P][V] in the row order of theta_micro:
+    S0, fractions, unit directions, f_intra (and D_par, D_perp)."""
+    tr = transforms(prob, th, c)
+    rows = [tr["S0"][None], tr["f"], tr["d"].reshape(3 * prob.K, prob.V), tr["fin"][None]]
+    if prob.learn_diffusivity:
+        rows += [tr["dpar"][None], tr["dperp"][None]]
+    return np.concatenate(rows, axis=0)
+
+
+def stitch_slabs(full_shape, z0, slabs, thetas, c: Constants = Constants()):
+    """Stitch per-slab fits into whole-volume maps (Sec. 2.5).
+
+    slabs[g] is the Problem of slab g (box nx x ny x nz_g, its own voxel
+    list), placed at slices z0[g].. of a volume of shape `full_shape`.
+    Returns (coords [V_out, 3] of the union of the slabs' voxels in raster
+    order, maps [P][V_out]).  A voxel seen by one slab takes its values.  In
+    an overlap the two slabs are blended with the `slab_weights`; the fibres
+    of the lighter slab (the upper one on a tie) are first matched to the
+    heavier slab's slots, taking for each slot in turn the unmatched fibre
+    with the largest |cos| (the lowest index on ties; decided in float32, the
+    precision of the fitted directions), and flipped to the same sign.  The
+    blended directions are renormalised; the output keeps the heavier slab's
+    slot order."""
+    nx, ny, nz = full_shape
+    K = slabs[0].K
+    w = slab_weights(list(z0), [p.shape[2] for p in slabs])
+    maps = [constrained_maps(p, th, c) for p, th in zip(slabs, thetas)]
+    src = {}
+    for g, p in enumerate(slabs):
+        for v, (i, j, k) in enumerate(p.coords):
+            r = (int(i) * ny + int(j)) * nz + int(z0[g]) + int(k)
+            src.setdefault(r, []).append((g, v, w[g][int(k)]))
+    keys = sorted(src)
+    C = K + 3
+    P = maps[0].shape[0]
+    out = np.zeros((P, len(keys)))
+    coords = np.zeros((len(keys), 3), dtype=np.int64)
+    for o, r in enumerate(keys):
+        coords[o] = (r // (ny * nz), (r // nz) % ny, r % nz)
+        s = src[r]
+        if len(s) == 1:
+            g, v, _ = s[0]
+            out[:, o] = maps[g][:, v]
+            continue
+        (ga, va, wa), (gb, vb, wb) = s
+        tot = wa + wb
+        wa, wb = wa / tot, wb / tot
+        if wa >= wb:
+            (gr, vr, wr), (go, vo, wo) = (ga, va, wa), (gb, vb, wb)
+        else:
+            (gr, vr, wr), (go, vo, wo) = (gb, vb, wb), (ga, va, wa)
+        mr, mo = maps[gr][:, vr], maps[go][:, vo]
+        res = wr * mr + wo * mo                       # S0, csf, gm, res, f_intra, D
+        dr = mr[1 + C:1 + C + 3 * K].reshape(K, 3)
+        do = mo[1 + C:1 + C + 3 * K].reshape(K, 3)
+        used = []
+        dots = dr.astype(np.float32) @ do.astype(np.float32).T      # float32 [K, K]
+        for k in range(K):
+            best, bj = -1.0, -1
+            for j in range(K):
+                if j not in used and abs(float(dots[k, j])) > best:
+                    best, bj = abs(float(dots[k, j])), j
+            used.append(bj)
+            sg = -1.0 if float(dots[k, bj]) < 0 else 1.0
+            res[3 + k] = wr * mr[3 + k] + wo * mo[3 + bj]
+            d = wr * dr[k] + wo * sg * do[bj]
+            res[1 + C + 3 * k:1 + C + 3 * k + 3] = d / np.linalg.norm(d)
+        out[:, o] = res
+    return coords, out
 
 
 # ----------------------------------------------------------------------------
