@@ -237,6 +237,36 @@ int32_t prism_rprop_step(float* p, const float* g, float* prev, float* step, int
                          float eta_minus, float eta_plus, float step_min, float step_max,
                          void* stream);
 
+/* Whole-volume slabs (Sec. 2.5): a volume too large for one fit is fitted as
+ * overlapping slabs along z, each an independent group with its own
+ * calibration, and the per-slab maps are blended where slabs overlap.
+ *
+ * prism_stitch_plan declares the groups of `h` to be such slabs: group g
+ * covers slices z0[g] .. z0[g] + nz_g - 1 of a volume nx x ny x nz (z0 a host
+ * array of n_groups entries, strictly increasing; every group with the
+ * volume's nx and ny, the same K and the same learn_diffusivity; no slice in
+ * more than two slabs).  It builds the stitch table on the device (allocates;
+ * not for graph capture; replaces an earlier plan) and returns in *n_out the
+ * number of output voxels: the union of the slabs' masked voxels, in raster
+ * order of the volume.
+ *
+ * prism_stitch_maps writes float32 maps [P][n_out] (device), P = 5 + 4K (+2),
+ * rows S0, fractions (csf, gm, wm_0..K-1, res), unit directions d_k (x, y, z),
+ * f_intra [, D_par, D_perp]: the constrained quantities of theta_micro.  A
+ * voxel of one slab takes that slab's values.  In an overlap of o slices the
+ * slabs are weighted by linear ramps, (s + 1)/(o + 1) at the s-th slice from
+ * a slab's edge (the two weights sum to one); the fibres of the lighter slab
+ * (the upper one on a tie) are matched to the heavier slab's slots, each slot
+ * in turn taking the unmatched fibre with the largest |cos| (lowest index on
+ * ties), flipped to the same sign, blended and renormalised; the output keeps
+ * the heavier slab's slot order.  (The paper states weighted averaging only;
+ * the ramp and the matching are readings.)  Asynchronous; allocates nothing;
+ * PRISM_E_INVALID before a plan. */
+int32_t prism_stitch_plan(prism_problem* h, int32_t nx, int32_t ny, int32_t nz, const int32_t* z0,
+                          int64_t* n_out);
+int32_t prism_stitch_maps(const prism_problem* h, const float* theta_micro, float* maps,
+                          void* stream);
+
 /* Optional per-kernel timing of the fused pass: when enabled, prism_loss_grad
  * records HIP events around each launch of the fused kernel on `stream`
  * (events are created here, not in the timed call).  prism_profile_read

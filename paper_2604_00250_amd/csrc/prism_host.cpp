@@ -80,11 +80,28 @@ struct prism_problem {
   float* d_ninv = nullptr;
   int32_t* d_grid = nullptr;
   int32_t* d_tri = nullptr;
+  std::vector<int32_t> coords_host;         // packed voxel coordinates of every group
+  // slab stitch table (prism_stitch_plan)
+  bool st_planned = false;
+  int64_t st_n_out = 0;
+  int32_t* d_st_g = nullptr;
+  int32_t* d_st_v = nullptr;
+  float* d_st_w = nullptr;
   // optional timing of the fused kernel
   bool prof = false;
   std::vector<hipEvent_t> ev;
   mutable int ev_used = 0;
 
+  void free_stitch() {
+    (void)hipFree(d_st_g);
+    (void)hipFree(d_st_v);
+    (void)hipFree(d_st_w);
+    d_st_g = nullptr;
+    d_st_v = nullptr;
+    d_st_w = nullptr;
+    st_n_out = 0;
+    st_planned = false;
+  }
   void free_plan() {
     (void)hipFree(d_items);
     (void)hipFree(d_tiles);
@@ -101,6 +118,7 @@ struct prism_problem {
     (void)hipFree(d_ninv);
     (void)hipFree(d_grid);
     (void)hipFree(d_tri);
+    free_stitch();
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
@@ -460,6 +478,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   h->n_y = y;
   h->ws_float = (size_t)wfl;
   h->acq_off = acq_off;
+  h->coords_host = coords;
   // default launch shape: split measurements across waves for small problems
   h->launch.vox_per_lane = vox >= 262144 ? 2 : 1;
   h->launch.n_split = vox < 65536 ? 4 : (vox < 262144 ? 2 : 1);
@@ -687,6 +706,102 @@ int32_t prism_rprop_step(float* p, const float* g, float* prev, float* step, int
   hipError_t e = launch_rprop(p, g, prev, step, n, eta_minus, eta_plus, step_min, step_max,
                               (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "Rprop launch");
+  return PRISM_OK;
+}
+
+int32_t prism_stitch_plan(prism_problem* h, int32_t nx, int32_t ny, int32_t nz, const int32_t* z0,
+                          int64_t* n_out) {
+  if (!h || !z0 || !n_out) return fail(PRISM_E_INVALID, "NULL argument");
+  const int G = (int)h->groups.size();
+  if (nx < 1 || ny < 1 || nz < 1 || nx > PRISM_MAX_EDGE || ny > PRISM_MAX_EDGE || nz > PRISM_MAX_EDGE)
+    return fail(PRISM_E_INVALID, "volume edges must be in 1..1023");
+  const GroupDev& g0 = h->groups[0];
+  for (int g = 0; g < G; ++g) {
+    const GroupDev& gd = h->groups[g];
+    if (gd.nx != nx || gd.ny != ny) return fail(PRISM_E_INVALID, "slab %d: box %dx%d differs from the volume's %dx%d", g, gd.nx, gd.ny, nx, ny);
+    if (gd.K != g0.K || gd.learn_d != g0.learn_d) return fail(PRISM_E_INVALID, "slab %d: K or learn_diffusivity differs", g);
+    if (z0[g] < 0 || z0[g] + gd.nz > nz) return fail(PRISM_E_INVALID, "slab %d: slices %d..%d outside the volume", g, z0[g], z0[g] + gd.nz - 1);
+    if (g > 0 && z0[g] <= z0[g - 1]) return fail(PRISM_E_INVALID, "slab starts must increase strictly");
+    if (g > 1 && z0[g] < z0[g - 2] + h->groups[g - 2].nz) return fail(PRISM_E_INVALID, "slab %d: a slice lies in more than two slabs", g);
+  }
+  // blend weights per slab and slice: linear ramps over the overlaps
+  std::vector<std::vector<float>> w(G);
+  for (int g = 0; g < G; ++g) {
+    const int a = z0[g], t = h->groups[g].nz;
+    const int o_lo = g > 0 ? std::max(0, z0[g - 1] + h->groups[g - 1].nz - a) : 0;
+    const int o_hi = g + 1 < G ? std::max(0, a + t - z0[g + 1]) : 0;
+    w[g].assign((size_t)t, 1.0f);
+    for (int k = 0; k < t; ++k) {
+      double x = 1.0;
+      if (o_lo) x = std::min(x, (k + 1.0) / (o_lo + 1.0));
+      if (o_hi) x = std::min(x, (double)(t - k) / (o_hi + 1.0));
+      w[g][(size_t)k] = (float)x;
+    }
+  }
+  // up to two sources per raster position of the volume
+  const size_t R = (size_t)nx * ny * nz;
+  std::vector<int32_t> ag(R, -1), av(R, -1), bg(R, -1), bv(R, -1);
+  for (int g = 0; g < G; ++g) {
+    const GroupDev& gd = h->groups[g];
+    for (int32_t v = 0; v < gd.V; ++v) {
+      const int32_t pc = h->coords_host[(size_t)gd.vox_off + v];
+      const size_t r = ((size_t)(pc & 1023) * ny + ((pc >> 10) & 1023)) * nz + z0[g] + ((pc >> 20) & 1023);
+      if (ag[r] < 0) {
+        ag[r] = g;
+        av[r] = v;
+      } else {
+        bg[r] = g;
+        bv[r] = v;
+      }
+    }
+  }
+  int64_t n = 0;
+  for (size_t r = 0; r < R; ++r) n += ag[r] >= 0;
+  std::vector<int32_t> sg((size_t)2 * n), sv((size_t)2 * n);
+  std::vector<float> sw((size_t)2 * n);
+  int64_t o = 0;
+  for (size_t r = 0; r < R; ++r) {
+    if (ag[r] < 0) continue;
+    const int zk = (int)(r % nz);
+    const float wa = w[ag[r]][(size_t)(zk - z0[ag[r]])];
+    const float wb = bg[r] >= 0 ? w[bg[r]][(size_t)(zk - z0[bg[r]])] : 0.0f;
+    sg[o] = ag[r];
+    sv[o] = av[r];
+    sg[n + o] = bg[r];
+    sv[n + o] = bv[r];
+    sw[o] = bg[r] >= 0 ? wa / (wa + wb) : 1.0f;
+    sw[n + o] = bg[r] >= 0 ? wb / (wa + wb) : 0.0f;
+    ++o;
+  }
+  h->free_stitch();
+  hipError_t e = upload(&h->d_st_g, sg);
+  if (e == hipSuccess) e = upload(&h->d_st_v, sv);
+  if (e == hipSuccess) e = upload(&h->d_st_w, sw);
+  if (e != hipSuccess) {
+    h->free_stitch();
+    return fail(PRISM_E_ALLOC, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  h->st_n_out = n;
+  h->st_planned = true;
+  *n_out = n;
+  return PRISM_OK;
+}
+
+int32_t prism_stitch_maps(const prism_problem* h, const float* theta_micro, float* maps, void* stream) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  if (!h->st_planned) return fail(PRISM_E_INVALID, "no stitch plan (call prism_stitch_plan first)");
+  if (h->st_n_out == 0) return PRISM_OK;
+  if (!theta_micro || !maps) return fail(PRISM_E_INVALID, "NULL device pointer");
+  StitchArgs a{};
+  a.groups = h->d_groups;
+  a.src_g = h->d_st_g;
+  a.src_v = h->d_st_v;
+  a.src_w = h->d_st_w;
+  a.th_micro = theta_micro;
+  a.maps = maps;
+  a.n_out = h->st_n_out;
+  hipError_t e = launch_stitch(a, h->groups[0].K, h->groups[0].learn_d, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stitch launch");
   return PRISM_OK;
 }
 

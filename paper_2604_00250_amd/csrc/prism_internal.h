@@ -115,6 +115,16 @@ struct ReduceArgs {
   int32_t n_groups;
 };
 
+struct StitchArgs {
+  const GroupDev* groups;
+  const int32_t* src_g;    // [2][n_out] source group (-1: none)
+  const int32_t* src_v;    // [2][n_out] source voxel within the group
+  const float* src_w;      // [2][n_out] normalised blend weight
+  const float* th_micro;
+  float* maps;             // [P][n_out]
+  int64_t n_out;
+};
+
 // launchers (prism_kernels.hip)
 hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s);
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
@@ -128,6 +138,7 @@ hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups,
                                  hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, int32_t* step, hipStream_t s);
+hipError_t launch_stitch(const StitchArgs& a, int K, int learn_d, hipStream_t s);
 hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n,
                         float em, float ep, float smin, float smax, hipStream_t s);
 

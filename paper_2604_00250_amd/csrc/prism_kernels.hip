@@ -9,6 +9,7 @@
 // k_reduce1/2 deterministic two-stage reduction of per-item records into the
 //             calibration gradient and the loss terms.
 // k_bias_tri  gradient of the 8^3 trilinear log-bias grid.
+// k_stitch    blend of per-slab maps into whole-volume maps (slab fitting).
 // k_adam, k_rprop  optimiser steps.
 #include "prism_device.h"
 #include "prism_internal.h"
@@ -922,6 +923,100 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// whole-volume slabs: blend the per-slab constrained maps (Sec. 2.5)
+// ---------------------------------------------------------------------------
+// constrained quantities of voxel v: S0, fractions, unit directions, f_intra [, D]
+template <int K, bool LD>
+__device__ __forceinline__ void maps_at(const GroupDev& g, const float* th_all, int v, float (&m)[4 * K + 5 + (LD ? 2 : 0)]) {
+  constexpr int C = K + 3;
+  const float* th = th_all + g.micro_off;
+  const int64_t V = g.V;
+  m[0] = softplus_f(th[v]);
+  float f[kMaxC];
+  softmax_at(th, V, C, v, f);
+#pragma unroll
+  for (int c = 0; c < C; ++c) m[1 + c] = f[c];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float x = th[(int64_t)row_v(C, k, 0) * V + v];
+    const float y = th[(int64_t)row_v(C, k, 1) * V + v];
+    const float z = th[(int64_t)row_v(C, k, 2) * V + v];
+    const float n2 = fmaf(x, x, fmaf(y, y, z * z));
+    const float in = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+    m[1 + C + 3 * k] = x * in;
+    m[2 + C + 3 * k] = y * in;
+    m[3 + C + 3 * k] = z * in;
+  }
+  m[1 + C + 3 * K] = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
+  if (LD) {
+    m[2 + C + 3 * K] = softplus_f(th[(int64_t)row_dpar(C, K) * V + v]);
+    m[3 + C + 3 * K] = softplus_f(th[(int64_t)(row_dpar(C, K) + 1) * V + v]);
+  }
+}
+
+// One thread per output voxel: one source is copied; two are blended with the
+// heavier slab as reference (the lower slab on a tie), the other slab's fibres
+// matched greedily by |cos| and sign-aligned.
+template <int K, bool LD>
+__global__ __launch_bounds__(256) void k_stitch(StitchArgs S) {
+  constexpr int C = K + 3;
+  constexpr int P = 4 * K + 5 + (LD ? 2 : 0);
+  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (o >= S.n_out) return;
+  const int ga = S.src_g[o], gb = S.src_g[S.n_out + o];
+  const float wa = S.src_w[o], wb = S.src_w[S.n_out + o];
+  float ma[P];
+  maps_at<K, LD>(S.groups[ga], S.th_micro, S.src_v[o], ma);
+  float out[P];
+  if (gb < 0) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) out[p] = ma[p];
+  } else {
+    float mb[P];
+    maps_at<K, LD>(S.groups[gb], S.th_micro, S.src_v[S.n_out + o], mb);
+    const bool a_ref = wa >= wb;
+    const float wr = a_ref ? wa : wb, wo = a_ref ? wb : wa;
+    float r[P], q[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      r[p] = a_ref ? ma[p] : mb[p];
+      q[p] = a_ref ? mb[p] : ma[p];
+      out[p] = wr * r[p] + wo * q[p];
+    }
+    int used = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float rx = r[1 + C + 3 * k], ry = r[2 + C + 3 * k], rz = r[3 + C + 3 * k];
+      float best = -1.0f, bdot = 0.0f, qf = 0.0f, qx = 0.0f, qy = 0.0f, qz = 0.0f;
+      int bj = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const float dot = rx * q[1 + C + 3 * j] + ry * q[2 + C + 3 * j] + rz * q[3 + C + 3 * j];
+        if (!(used & (1 << j)) && fabsf(dot) > best) {
+          best = fabsf(dot);
+          bdot = dot;
+          bj = j;
+          qf = q[3 + j];
+          qx = q[1 + C + 3 * j];
+          qy = q[2 + C + 3 * j];
+          qz = q[3 + C + 3 * j];
+        }
+      }
+      used |= 1 << bj;
+      const float sg = bdot < 0.0f ? -wo : wo;
+      out[3 + k] = wr * r[3 + k] + wo * qf;
+      const float dx = wr * rx + sg * qx, dy = wr * ry + sg * qy, dz = wr * rz + sg * qz;
+      const float in = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      out[1 + C + 3 * k] = dx * in;
+      out[2 + C + 3 * k] = dy * in;
+      out[3 + C + 3 * k] = dz * in;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) S.maps[(int64_t)p * S.n_out + o] = out[p];
+}
+
+// ---------------------------------------------------------------------------
 // deterministic two-stage reduction of the item records
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce1(ReduceArgs R) {
@@ -1308,6 +1403,29 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
   return hipGetLastError();
+}
+
+template <int K>
+static hipError_t launch_stitch_k(const StitchArgs& a, int learn_d, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.n_out + 255) / 256);
+  if (learn_d)
+    hipLaunchKernelGGL((k_stitch<K, true>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_stitch<K, false>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stitch(const StitchArgs& a, int K, int learn_d, hipStream_t s) {
+  if (a.n_out <= 0) return hipSuccess;
+  switch (K) {
+    case 1: return launch_stitch_k<1>(a, learn_d, s);
+    case 2: return launch_stitch_k<2>(a, learn_d, s);
+    case 3: return launch_stitch_k<3>(a, learn_d, s);
+    case 4: return launch_stitch_k<4>(a, learn_d, s);
+    case 5: return launch_stitch_k<5>(a, learn_d, s);
+    case 6: return launch_stitch_k<6>(a, learn_d, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n, float em,

@@ -168,6 +168,22 @@ class Problem:
     def synthesize_ptr(self, th_micro, th_cal, yhat, stream):
         L.check(L.lib().prism_synthesize(self.handle, th_micro, th_cal, yhat, stream))
 
+    def stitch_plan(self, shape, z0) -> int:
+        """Declare the groups to be z-slabs of a volume `shape` starting at
+        slices `z0`; returns the number of stitched output voxels."""
+        z = np.ascontiguousarray(z0, dtype=np.int32)
+        if z.shape != (self.n_groups,):
+            raise ValueError("one slab start per group")
+        n = ctypes.c_int64()
+        nx, ny, nz = (int(s) for s in shape)
+        L.check(L.lib().prism_stitch_plan(self.handle, nx, ny, nz,
+                                          z.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(n)))
+        self.n_stitch = int(n.value)
+        return self.n_stitch
+
+    def stitch_maps_ptr(self, th_micro, maps, stream):
+        L.check(L.lib().prism_stitch_maps(self.handle, th_micro, maps, stream))
+
     def profile(self, enable: bool, max_launches: int = 4096):
         L.check(L.lib().prism_profile_enable(self.handle, int(enable), int(max_launches)))
 
@@ -269,6 +285,17 @@ class DeviceState:
         pm, pc, _, _ = self.ptrs()
         self.prob.synthesize_ptr(pm, pc, out.data_ptr(), self._s())
         return out
+
+    def stitch_maps(self, out=None):
+        """Whole-volume maps [P][n_out] of the current parameters (after
+        Problem.stitch_plan), on the device."""
+        g0 = self.prob.groups[0]
+        P = n_params_vox(g0.K, bool(g0.learn_diffusivity))
+        n = self.prob.n_stitch
+        if out is None:
+            out = self.torch.empty((P, max(n, 1)), dtype=self.torch.float32, device=self.device)
+        self.prob.stitch_maps_ptr(self.params.data_ptr(), out.data_ptr(), self._s())
+        return out[:, :n]
 
     # host views
     def grads_host(self):
