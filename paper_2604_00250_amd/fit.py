@@ -25,8 +25,10 @@ class Loop:
 
     def __init__(self, state: DeviceState, lr: float = 1e-2, optimizer: str = "adam",
                  betas=(0.9, 0.999), eps: float = 1e-8, history: int = 0,
-                 rprop=(0.5, 1.2, 1e-6, 50.0)):
+                 rprop=(0.5, 1.2, 1e-6, 50.0), calibrate: bool = True):
         self.st = state
+        # calibrate=False keeps theta_cal fixed: the optimiser sees theta_micro only
+        self.n_opt = state.n_micro + (state.n_cal if calibrate else 0)
         self.lr = lr
         self.optimizer = optimizer
         self.betas = betas
@@ -56,9 +58,9 @@ class Loop:
         st.loss_grad()
         self._record()
         if self.optimizer == "adam":
-            st.adam(self.lr, self.betas[0], self.betas[1], self.eps)
+            st.adam(self.lr, self.betas[0], self.betas[1], self.eps, n=self.n_opt)
         else:
-            n = st.n_micro + st.n_cal
+            n = self.n_opt
             em, ep, smin, smax = self.rprop
             rprop_step_ptr(st.params.data_ptr(), st.grad.data_ptr(), self.prev.data_ptr(),
                            self.rstep.data_ptr(), n, em, ep, smin, smax, st._s())
@@ -90,11 +92,12 @@ class Loop:
 
 
 def fit(state: DeviceState, iterations: int, lr: float = 1e-2, graph: bool = True,
-        optimizer: str = "adam") -> torch.Tensor:
-    """Run `iterations` optimiser iterations; returns the device loss history."""
+        optimizer: str = "adam", calibrate: bool = True) -> torch.Tensor:
+    """Run `iterations` optimiser iterations; returns the device loss history.
+    calibrate=False holds the calibration parameters at their current values."""
     if graph:
         snap = snapshot(state)
-        loop = Loop(state, lr=lr, optimizer=optimizer, history=iterations)
+        loop = Loop(state, lr=lr, optimizer=optimizer, history=iterations, calibrate=calibrate)
         loop.capture()                      # the warm-up ran one iteration: restore, then replay
         restore(state, snap)
         if optimizer == "rprop":
@@ -104,7 +107,7 @@ def fit(state: DeviceState, iterations: int, lr: float = 1e-2, graph: bool = Tru
         loop.hist.zero_()
         loop.replay(iterations)
     else:
-        loop = Loop(state, lr=lr, optimizer=optimizer, history=iterations)
+        loop = Loop(state, lr=lr, optimizer=optimizer, history=iterations, calibrate=calibrate)
         for _ in range(iterations):
             loop.step_eager()
     torch.cuda.synchronize(state.device)

@@ -136,7 +136,8 @@ def electrostatic_hemisphere(n: int, rng, steps: int = 2000) -> np.ndarray:
 
 def make_acquisition(kind: str, rng) -> Acquisition:
     """kind: 'single33' (1 b0 + 32 @ b=1000), 'two96' (6 b0 + 45 @ 1000 + 45 @ 2000),
-    'three288' (18 b0 + 90 @ 1000/2000/3000), 'three193' (1 b0 + 64 @ 1000/2000/3000)."""
+    'three288' (18 b0 + 90 @ 1000/2000/3000), 'three193' (1 b0 + 64 @ 1000/2000/3000),
+    'hardi160' (10 b0 + 150 @ b=2000, the shape of a single-shell HARDI scan)."""
     if kind == "single33":
         shells = [(0.0, 1), (1000.0, 32)]
         dirs = [np.array([[1.0, 0.0, 0.0]]), electrostatic_hemisphere(32, rng)]
@@ -145,6 +146,7 @@ def make_acquisition(kind: str, rng) -> Acquisition:
             "two96": [(0.0, 6), (1000.0, 45), (2000.0, 45)],
             "three288": [(0.0, 18), (1000.0, 90), (2000.0, 90), (3000.0, 90)],
             "three193": [(0.0, 1), (1000.0, 64), (2000.0, 64), (3000.0, 64)],
+            "hardi160": [(0.0, 10), (2000.0, 150)],
         }[kind]
         dirs = []
         for b, cnt in shells:
@@ -467,12 +469,14 @@ def _separate(dirs, min_angle=20.0):
     return dirs
 
 
-def config2(seed=None, shape=(145, 174, 145), target=741_000, with_y=True) -> Workload:
+def config2(seed=None, shape=(145, 174, 145), target=741_000, with_y=True, acq_kind="three288") -> Workload:
     """Whole-brain-shaped volume: ellipsoid mask of ~741k voxels, smooth tissue
     maps (CSF shell, GM rim, WM core with 1-3 fibres following smooth direction
-    fields), N=288 three-shell, K=3, MSE, calibration on at identity, SNR 30."""
+    fields), N=288 three-shell, K=3, MSE, calibration on at identity, SNR 30.
+    `shape`, `target` and `acq_kind` give smaller or differently sampled
+    volumes of the same construction."""
     r_acq, r_tis, r_dir, r_noise, r_cal, r_init = streams(2, seed)
-    acq = make_acquisition("three288", r_acq)
+    acq = make_acquisition(acq_kind, r_acq)
     mask, rho_full = whole_brain_mask(shape, r_tis, target=target)
     V = int(mask.sum())
     rho = rho_full[mask] + 0.03 * smooth_field(shape, r_tis, 4.0)[mask]
@@ -622,6 +626,65 @@ def sub_box(g: Group, corner, edge) -> Group:
             th[key] = a[..., keep].copy()
     return dataclasses.replace(g, shape=(edge, edge, edge), mask=mask, y=g.y[:, keep].copy(),
                                theta=th, truth=None)
+
+
+CROSSING_ANGLES = tuple(range(15, 95, 5))   # 16 crossing angles, degrees
+
+
+def crossing_benchmark(snr: float = 30.0, seed=None, per_angle: int = 200, n_single: int = 200,
+                       mode: str = "mse", gain_sigma: float = 0.0, angles=CROSSING_ANGLES,
+                       K: int = 2) -> Workload:
+    """Crossing-fibre voxels on the shape of the paper's synthetic benchmark
+    (Sec. 3 dataset i, Table 1): `per_angle` voxels at each crossing angle
+    (15-90 degrees in 5-degree steps) and `n_single` single-fibre voxels;
+    N = 193 (1 b0 + 64 directions at each of b = 1000, 2000, 3000); K = 2;
+    Rician noise at `snr`.  Two crossing fibres share the WM fraction equally;
+    d_par ~ U(1.5, 2.2), d_perp ~ U(0.3, 0.7); WM carries U(0.7, 0.9) of the
+    signal, the rest is split by Dirichlet(1) between the three balls.  With
+    `gain_sigma` > 0 every diffusion-weighted measurement is multiplied by a
+    gain drawn from N(1, gain_sigma) (the artifact sweep of Sec. 4; b0 stays
+    the normaliser).  Voxels fill a (rows, per_angle, 1) box, one row per
+    angle and a last row of single fibres, and are fitted independently (no
+    neighbourhood).  The paper's DIPY-generated set is not available; this
+    generator reproduces its shape only."""
+    r_acq, r_tis, r_dir, r_noise, r_cal, r_init = streams(5, seed)
+    acq = make_acquisition("three193", r_acq)
+    if n_single > per_angle:
+        raise ValueError("n_single must not exceed per_angle (one box row each)")
+    rows = len(angles) + (1 if n_single else 0)
+    mask = np.zeros((rows, per_angle, 1), dtype=bool)
+    mask[: len(angles)] = True
+    if n_single:
+        mask[len(angles), :n_single] = True
+    V = int(mask.sum())
+    row = np.argwhere(mask)[:, 0]
+    crossing = row < len(angles)
+    angle = np.where(crossing, np.asarray(angles, dtype=np.float64)[np.minimum(row, len(angles) - 1)], 0.0)
+    dirs = np.zeros((2, V, 3))
+    dirs[0] = uniform_sphere(V, r_dir)
+    dirs[1] = _rotate_towards(dirs[0], angle, r_dir)
+    n_fib = np.where(crossing, 2, 1)
+    wm = r_tis.uniform(0.7, 0.9, size=V)
+    frac = np.zeros((5, V))
+    frac[:3] = r_tis.dirichlet(np.ones(3), size=V).T * (1.0 - wm)[None]
+    frac[3] = np.where(crossing, 0.5 * wm, wm)
+    frac[4] = np.where(crossing, 0.5 * wm, 0.0)
+    truth = tissue_truth(V, r_tis, max_fib=2, n_fib=n_fib, dirs=dirs, frac=frac)
+    truth["angle"] = angle
+    S = truth_signal(acq, truth)
+    if gain_sigma > 0:
+        gain = np.where(acq.bval > 0, r_cal.normal(1.0, gain_sigma, size=acq.n), 1.0)
+        S = gain[:, None] * S
+        truth["gain"] = gain
+    sigma = 1.0 / snr
+    y = rician(S, sigma, r_noise)
+    theta = init_theta(V, K, acq.n, 0, r_init, sigma_init=2.0 * sigma if mode == "nll" else 0.0)
+    g = Group(shape=mask.shape, mask=mask, acq=acq, K=K, mode=mode, bias="none", neighbourhood=0,
+              priors=("rep", "sparse", "cal"), y=y, theta=theta, truth=truth, sigma_true=sigma)
+    name = f"crossing{len(angles)}x{per_angle}+{n_single}_n193_k{K}_{mode}_snr{snr:g}"
+    if gain_sigma > 0:
+        name += f"_gain{gain_sigma:g}"
+    return Workload(name=name, groups=[g], iterations=300, description=name)
 
 
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}

@@ -270,8 +270,8 @@ class DeviceState:
         self.prob.loss_grad_ptr(self.y.data_ptr(), pm, pc, self.loss.data_ptr(), gm, gc,
                                 self.ws.data_ptr(), self.ws_bytes, self.status.data_ptr(), self._s())
 
-    def adam(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
-        n = self.n_micro + self.n_cal
+    def adam(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, n=None):
+        n = self.n_micro + self.n_cal if n is None else int(n)
         adam_step_ptr(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                       n, lr, beta1, beta2, eps, self.step.data_ptr(), self._s())
 
