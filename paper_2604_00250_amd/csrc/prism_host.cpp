@@ -479,8 +479,9 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   h->ws_float = (size_t)wfl;
   h->acq_off = acq_off;
   h->coords_host = coords;
-  // default launch shape: split measurements across waves for small problems
-  h->launch.vox_per_lane = vox >= 262144 ? 2 : 1;
+  // default launch shape: one voxel per lane (three waves per SIMD for the
+  // common variants); split measurements across waves for small problems
+  h->launch.vox_per_lane = 1;
   h->launch.n_split = vox < 65536 ? 4 : (vox < 262144 ? 2 : 1);
   if (n_groups > 64) h->launch.n_split = 0;  // many groups: split per item size
   h->launch.item_vox = 0;

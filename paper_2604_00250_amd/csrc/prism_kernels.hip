@@ -334,35 +334,49 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     const int cnt = min(kTile, ne - n0);
     v4f Da = {0.0f, 0.0f, 0.0f, 0.0f}, Db = {0.0f, 0.0f, 0.0f, 0.0f};
     float lacc = 0.0f, sacc = 0.0f;
-    for (int t0 = 0; t0 < cnt; t0 += kPf) {
+    // one measurement: the ring slot u is refilled (measurement n + kPf) only after
+    // its value has been consumed, so the load can target the slot's register
+    // directly and the wait for it lands kPf measurements later
+    auto body = [&](int t, float (&slot)[VL]) {
+      const int n = n0 + t;
+      const float4 a = acq[3 * n + 0];
+      const float4 b = acq[3 * n + 1];
+      const float4 c = acq[3 * n + 2];
+      float pa = 0.0f, pb = 0.0f;
 #pragma unroll
-      for (int u = 0; u < kPf; ++u) {
-        const int t = t0 + u;
-        if (t < cnt) {
-          const int n = n0 + t;
-          float yv[VL];
+      for (int j = 0; j < VL; ++j) {
+        float tl, ts, sq, sd;
+        pair<K, MODE, LD>(x[j], acc[j], slot[j], a, b, c, inv_s2, tl, ts, sq, sd);
+        lacc = fmaf(valid[j], tl, lacc);
+        if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
+        pa = fmaf(valid[j], sq, pa);
+        pb = fmaf(valid[j], sd, pb);
+      }
 #pragma unroll
-          for (int j = 0; j < VL; ++j) {
-            yv[j] = yr[u][j];
-            yr[u][j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: always in bounds
-          }
-          const float4 a = acq[3 * n + 0];
-          const float4 b = acq[3 * n + 1];
-          const float4 c = acq[3 * n + 2];
-          float pa = 0.0f, pb = 0.0f;
+      for (int j = 0; j < VL; ++j) slot[j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: in bounds
+      const float sel = lane16 == t ? 1.0f : 0.0f;
+      Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
+      Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+    };
+    if (MODE == kMSE) {
+      // whole groups of kPf measurements: straight-line code, no per-measurement branch
+      const int full = cnt - cnt % kPf;
+      for (int t0 = 0; t0 < full; t0 += kPf) {
 #pragma unroll
-          for (int j = 0; j < VL; ++j) {
-            float tl, ts, sq, sd;
-            pair<K, MODE, LD>(x[j], acc[j], yv[j], a, b, c, inv_s2, tl, ts, sq, sd);
-            lacc = fmaf(valid[j], tl, lacc);
-            if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
-            pa = fmaf(valid[j], sq, pa);
-            pb = fmaf(valid[j], sd, pb);
-          }
-          const float sel = lane16 == t ? 1.0f : 0.0f;
-          Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
-          Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+        for (int u = 0; u < kPf; ++u) {
+          body(t0 + u, yr[u]);
+          __builtin_amdgcn_sched_barrier(0);
         }
+      }
+      // the tile's last cnt % kPf measurements (only in the final tile of a range)
+#pragma unroll
+      for (int u = 0; u + 1 < kPf; ++u)
+        if (full + u < cnt) body(full + u, yr[u]);
+    } else {
+      for (int t0 = 0; t0 < cnt; t0 += kPf) {
+#pragma unroll
+        for (int u = 0; u < kPf; ++u)
+          if (t0 + u < cnt) body(t0 + u, yr[u]);
       }
     }
     float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);

@@ -1,13 +1,20 @@
-"""Write a short markdown summary of a rocprofv3 --stats kernel table.
+"""Short markdown summaries of rocprofv3 output for the fused kernel.
 
-    python -m paper_2604_00250_amd.profile_summary STATS_CSV BENCH_JSON OUT_MD "COMMAND"
+    python -m paper_2604_00250_amd.profile_summary stats   STATS_CSV BENCH_JSON OUT_MD "COMMAND"
+    python -m paper_2604_00250_amd.profile_summary traffic FETCH_CSV WRITE_CSV OUT_MD KERNEL WORKLOAD "CMD_F" "CMD_W"
+    python -m paper_2604_00250_amd.profile_summary valu    AGENT_CSV BENCH_JSON OUT_MD KERNEL "COMMANDS" PASS_CSV...
+
+stats: the kernel table of `rocprofv3 --kernel-trace --stats`.  traffic: HBM
+bytes per dispatch from FETCH_SIZE / WRITE_SIZE, scaled by what the same
+counters read for the microbenchmark's copy of a known size.  valu: issue
+and utilisation figures of one kernel from SQ counter passes.
 """
 import csv
 import json
 import sys
 
 
-def main(stats_csv, bench_json, out_md, command):
+def stats_summary(stats_csv, bench_json, out_md, command):
     rows = list(csv.DictReader(open(stats_csv)))
     b = json.load(open(bench_json))
     rf = b.get("roofline", {})
@@ -27,10 +34,6 @@ def main(stats_csv, bench_json, out_md, command):
                     f"{float(kp[0]['AverageNs']) / 1e3:.0f} us.\n")
 
 
-if __name__ == "__main__":
-    main(*sys.argv[1:5])
-
-
 def kernel_source_hash(root=None) -> str:
     """SHA-1 of the kernel sources (a profile's counters describe this build only)."""
     import hashlib
@@ -43,16 +46,18 @@ def kernel_source_hash(root=None) -> str:
     return h.hexdigest()[:12]
 
 
+def _per_kernel(path):
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        agg.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
 def traffic_summary(fetch_csv, write_csv, out_md, kernel, command_fetch, command_write, workload):
     """FETCH_SIZE / WRITE_SIZE per dispatch of `kernel`, scaled by what the same
     counters read for the microbenchmark's copy of a known size (2 x 1 GiB)."""
-    def per_kernel(path):
-        agg = {}
-        for r in csv.DictReader(open(path)):
-            agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return {k: sum(v) / len(v) for k, v in agg.items()}
-    f = per_kernel(fetch_csv)
-    w = per_kernel(write_csv)
+    f = {k[0]: v for k, v in _per_kernel(fetch_csv).items()}
+    w = {k[0]: v for k, v in _per_kernel(write_csv).items()}
     kib = 1 << 30 >> 10  # the copy reads 1 GiB and writes 1 GiB
     sf = kib / f["mb_copy_kernel"]
     sw = kib / w["mb_copy_kernel"]
@@ -69,3 +74,73 @@ def traffic_summary(fetch_csv, write_csv, out_md, kernel, command_fetch, command
         o.write(f"traffic_bytes_per_dispatch: {traffic:.6e}\n")
         o.write(f"kernel_source_sha1: {kernel_source_hash()}\n")
     return traffic
+
+
+def valu_summary(agent_csv, bench_json, out_md, kernel, commands, pass_csvs):
+    """Issue counts per (voxel, measurement) pair and busy fractions of `kernel`
+    from SQ counter passes (averages over its dispatches).  Elapsed cycles are
+    GRBM_GUI_ACTIVE / XCDs; SQ_ACTIVE_INST_VALU and SQ_WAVE_CYCLES count quad
+    cycles summed over waves."""
+    agent = [r for r in csv.DictReader(open(agent_csv)) if r["Agent_Type"].strip('"') == "GPU"][0]
+    n_xcc = int(agent["Num_Xcc"])
+    simds = int(agent["Cu_Count"]) * int(agent["Simd_Per_Cu"])
+    c = {}
+    for p in pass_csvs:
+        for (k, name), v in _per_kernel(p).items():
+            if k == kernel:
+                c.setdefault(name, v)
+    b = json.load(open(bench_json))
+    cfg = b["config"]
+    pairs = cfg["voxels"] * cfg["measurements"]
+    cyc = c["GRBM_GUI_ACTIVE"] / n_xcc
+    lanes = 64.0
+    per_pair = lambda name: c[name] * lanes / pairs  # noqa: E731
+    busy_valu = c["SQ_ACTIVE_INST_VALU"] * 4 / (simds * cyc)
+    waves = c["SQ_WAVE_CYCLES"] * 4 / (simds * cyc)
+    mfma = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc) if "SQ_VALU_MFMA_BUSY_CYCLES" in c else None
+    flops = None
+    if "SQ_INSTS_VALU_FMA_F32" in c:
+        flops = (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"] + c["SQ_INSTS_VALU_MUL_F32"]
+                 + c["SQ_INSTS_VALU_TRANS_F32"]) * lanes
+    rows = [
+        ("VALU instructions per pair", per_pair("SQ_INSTS_VALU")),
+        ("  of which FP32 transcendental (exp, log, rcp)", per_pair("SQ_INSTS_VALU_TRANS_F32")),
+        ("  of which FP32 FMA", per_pair("SQ_INSTS_VALU_FMA_F32") if "SQ_INSTS_VALU_FMA_F32" in c else None),
+        ("  of which FP32 MUL", per_pair("SQ_INSTS_VALU_MUL_F32") if "SQ_INSTS_VALU_MUL_F32" in c else None),
+        ("  of which FP32 ADD", per_pair("SQ_INSTS_VALU_ADD_F32") if "SQ_INSTS_VALU_ADD_F32" in c else None),
+        ("MFMA instructions per pair", per_pair("SQ_INSTS_MFMA")),
+        ("LDS instructions per pair", per_pair("SQ_INSTS_LDS")),
+        ("SALU instructions per pair", per_pair("SQ_INSTS_SALU")),
+        ("vector memory instructions per pair", per_pair("SQ_INSTS_VMEM")),
+        ("elapsed cycles per dispatch (GRBM_GUI_ACTIVE / XCDs)", cyc),
+        ("VALU busy (fraction of SIMD-cycles)", busy_valu),
+        ("matrix core busy (fraction of SIMD-cycles)", mfma),
+        ("mean resident waves per SIMD", waves),
+    ]
+    with open(out_md, "w") as o:
+        o.write(f"# VALU, transcendental and matrix-core use of {kernel} on {cfg['workload']}\n\n")
+        o.write(f"{cfg['voxels']:,} voxels x {cfg['measurements']} measurements = {pairs:,} pairs per "
+                f"dispatch; {simds} SIMDs in {n_xcc} XCDs.  Counter passes (repository root `$R`):\n\n```\n"
+                + commands + "\n```\n\n| quantity | value |\n|---|---|\n")
+        for name, v in rows:
+            if v is None:
+                continue
+            o.write(f"| {name} | {v:.4g} |\n")
+        if flops is not None:
+            o.write(f"| FP32 VALU FLOPs per pair (FMA = 2) | {flops / pairs:.4g} |\n")
+        o.write(f"\nkernel_source_sha1: {kernel_source_hash()}\n")
+    return dict(rows)
+
+
+if __name__ == "__main__":
+    cmd, args = sys.argv[1], sys.argv[2:]
+    if cmd == "stats":
+        stats_summary(*args[:4])
+    elif cmd == "traffic":
+        fetch, write, out, kernel, workload, cf, cw = args[:7]
+        traffic_summary(fetch, write, out, kernel, cf, cw, workload)
+    elif cmd == "valu":
+        agent, bench, out, kernel, commands = args[:5]
+        valu_summary(agent, bench, out, kernel, commands, args[5:])
+    else:
+        raise SystemExit(f"unknown summary {cmd}")
