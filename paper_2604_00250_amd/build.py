@@ -4,7 +4,10 @@
 
 Every HIP translation unit is compiled with packed-FP32 instructions turned
 off (``-target-feature -packed-fp32-ops``): the kernels are written for
-scalar FP32 issue.
+scalar FP32 issue.  Matrix-core accumulators are kept in ordinary VGPRs
+(``-amdgpu-mfma-vgpr-form``): the fused pass uses the matrix core only as a
+reduction engine, and the accumulation-register form made the compiler
+shuffle the accumulators between registers on every measurement group.
 """
 import os
 import shutil
@@ -30,6 +33,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(HERE, "..", "include")]
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")

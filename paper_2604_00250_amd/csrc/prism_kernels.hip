@@ -330,55 +330,50 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
   for (int u = 0; u < kPf; ++u)
 #pragma unroll
     for (int j = 0; j < VL; ++j) yr[u][j] = yp[j][(int64_t)min(nb + u, ne - 1) * V];
-  for (int n0 = nb; n0 < ne; n0 += kTile) {
-    const int cnt = min(kTile, ne - n0);
-    v4f Da = {0.0f, 0.0f, 0.0f, 0.0f}, Db = {0.0f, 0.0f, 0.0f, 0.0f};
-    float lacc = 0.0f, sacc = 0.0f;
-    // one measurement: the ring slot u is refilled (measurement n + kPf) only after
-    // its value has been consumed, so the load can target the slot's register
-    // directly and the wait for it lands kPf measurements later
-    auto body = [&](int t, float (&slot)[VL]) {
-      const int n = n0 + t;
-      const float4 a = acq[3 * n + 0];
-      const float4 b = acq[3 * n + 1];
-      const float4 c = acq[3 * n + 2];
-      float pa = 0.0f, pb = 0.0f;
+  v4f Da, Db;
+  float lacc, sacc;
+  int n0 = nb;
+  // one measurement: the ring slot u is refilled (measurement n + kPf) only after
+  // its value has been consumed, so the load can target the slot's register
+  // directly and the wait for it lands kPf measurements later
+  auto body = [&](int t, float (&slot)[VL]) {
+    const int n = n0 + t;
+    const float4 a = acq[3 * n + 0];
+    const float4 b = acq[3 * n + 1];
+    const float4 c = acq[3 * n + 2];
+    float pa = 0.0f, pb = 0.0f;
 #pragma unroll
-      for (int j = 0; j < VL; ++j) {
-        float tl, ts, sq, sd;
-        pair<K, MODE, LD>(x[j], acc[j], slot[j], a, b, c, inv_s2, tl, ts, sq, sd);
-        lacc = fmaf(valid[j], tl, lacc);
-        if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
-        pa = fmaf(valid[j], sq, pa);
-        pb = fmaf(valid[j], sd, pb);
-      }
-#pragma unroll
-      for (int j = 0; j < VL; ++j) slot[j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: in bounds
-      const float sel = lane16 == t ? 1.0f : 0.0f;
-      Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
-      Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    };
-    if (MODE == kMSE) {
-      // whole groups of kPf measurements: straight-line code, no per-measurement branch
-      const int full = cnt - cnt % kPf;
-      for (int t0 = 0; t0 < full; t0 += kPf) {
-#pragma unroll
-        for (int u = 0; u < kPf; ++u) {
-          body(t0 + u, yr[u]);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      // the tile's last cnt % kPf measurements (only in the final tile of a range)
-#pragma unroll
-      for (int u = 0; u + 1 < kPf; ++u)
-        if (full + u < cnt) body(full + u, yr[u]);
-    } else {
-      for (int t0 = 0; t0 < cnt; t0 += kPf) {
-#pragma unroll
-        for (int u = 0; u < kPf; ++u)
-          if (t0 + u < cnt) body(t0 + u, yr[u]);
-      }
+    for (int j = 0; j < VL; ++j) {
+      float tl, ts, sq, sd;
+      pair<K, MODE, LD>(x[j], acc[j], slot[j], a, b, c, inv_s2, tl, ts, sq, sd);
+      lacc = fmaf(valid[j], tl, lacc);
+      if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
+      pa = fmaf(valid[j], sq, pa);
+      pb = fmaf(valid[j], sd, pb);
     }
+#pragma unroll
+    for (int j = 0; j < VL; ++j) slot[j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: in bounds
+    const float sel = lane16 == t ? 1.0f : 0.0f;
+    Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
+    Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+  };
+  auto tile_begin = [&]() {
+    Da = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    Db = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    lacc = 0.0f;
+    sacc = 0.0f;
+  };
+  // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
+  auto group = [&](int t0) {
+#pragma unroll
+    for (int u = 0; u < kPf; ++u) {
+      body(t0 + u, yr[u]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  // wave totals of the tile's per-measurement sums: lane l of the accumulator
+  // tile holds rows 4(l/16).. of column l%16
+  auto tile_end = [&](int cnt) {
     float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);
     float rb = (Db[0] + Db[1]) + (Db[2] + Db[3]);
     ra += __shfl_xor(ra, 16, 64);
@@ -391,6 +386,38 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     }
     dloss += (double)lacc;
     dsig += (double)sacc;
+  };
+  if (MODE == kMSE) {
+    // whole tiles: every path into the loop has the ring's loads in flight in slot
+    // order, so each wait is for exactly one slot
+    for (; n0 + kTile <= ne; n0 += kTile) {
+      tile_begin();
+#pragma unroll 1
+      for (int t0 = 0; t0 < kTile; t0 += kPf) group(t0);
+      tile_end(kTile);
+    }
+    if (n0 < ne) {  // the range's last, partial tile
+      const int cnt = ne - n0;
+      const int full = cnt - cnt % kPf;
+      tile_begin();
+#pragma unroll 1
+      for (int t0 = 0; t0 < full; t0 += kPf) group(t0);
+#pragma unroll
+      for (int u = 0; u + 1 < kPf; ++u)
+        if (full + u < cnt) body(full + u, yr[u]);
+      tile_end(cnt);
+    }
+  } else {
+    for (; n0 < ne; n0 += kTile) {
+      const int cnt = min(kTile, ne - n0);
+      tile_begin();
+      for (int t0 = 0; t0 < cnt; t0 += kPf) {
+#pragma unroll
+        for (int u = 0; u < kPf; ++u)
+          if (t0 + u < cnt) body(t0 + u, yr[u]);
+      }
+      tile_end(cnt);
+    }
   }
 }
 
