@@ -228,6 +228,26 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
 int32_t prism_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                         float beta1, float beta2, float eps, int32_t* step, void* stream);
 
+/* One Adam iteration of the fit: the loss terms at theta (as prism_loss_grad
+ * reports them) and the Adam update of theta_micro and, if update_cal != 0,
+ * theta_cal, after which step[0] has advanced by one.  The results are
+ * bitwise those of prism_loss_grad followed by prism_adam_step over the same
+ * parameters.  The per-voxel parameters are updated inside the fused pass, so
+ * their gradient never goes through memory; when a group uses the continuity
+ * prior (which reads neighbouring voxels' parameters during the pass) the call
+ * runs the two steps one after the other and grad_micro receives the
+ * per-voxel gradient.  Arguments as for prism_loss_grad and prism_adam_step;
+ * m_micro, v_micro [n_micro] and m_cal, v_cal [n_cal] are the Adam moments
+ * (device), grad_micro [n_micro] (device) is scratch for the unfused case,
+ * grad_cal [n_cal] receives the calibration gradient.  Asynchronous;
+ * allocates nothing; graph-capturable. */
+int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* theta_micro,
+                             float* theta_cal, float* m_micro, float* v_micro, float* m_cal,
+                             float* v_cal, int32_t* step, float lr, float beta1, float beta2,
+                             float eps, int32_t update_cal, double* loss, float* grad_micro,
+                             float* grad_cal, void* workspace, size_t workspace_bytes,
+                             uint32_t* status, void* stream);
+
 /* Rprop (Riedmiller & Braun 1993; the paper's solver, Sec. 2.5), PyTorch's
  * variant: per coordinate, s = g * prev; step *= eta_plus if s > 0, eta_minus
  * if s < 0; step clamped to [step_min, step_max]; where s < 0 the gradient is

@@ -456,8 +456,10 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
       grid.insert(grid.end(), idx.begin(), idx.end());
       h->tri_groups.push_back(gi);
     }
-    g.w_off = wfl;  // [C][V] residual weights, then [C][V] fractions
-    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += 2 * (int64_t)g.C * V;
+    g.cs = (g.C + 3) & ~3;
+    wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned rows
+    g.w_off = wfl;  // [V][cs] residual weights, then [V][cs] fractions
+    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += 2 * (int64_t)g.cs * V;
     g.glb_off = wfl;
     if (d.bias == PRISM_BIAS_TRILINEAR8) wfl += V;
     wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned acquisition table
@@ -619,19 +621,14 @@ int32_t prism_synthesize(const prism_problem* h, const float* theta_micro, const
   return PRISM_OK;
 }
 
-int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* theta_micro,
-                        const float* theta_cal, double* loss, float* grad_micro, float* grad_cal,
-                        void* workspace, size_t workspace_bytes, uint32_t* status, void* stream) {
-  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
-  if ((h->n_y && !y) || (h->n_micro && (!theta_micro || !grad_micro)) || !theta_cal || !grad_cal ||
-      !loss || !status)
-    return fail(PRISM_E_INVALID, "NULL device pointer");
-  size_t need = 0;
-  prism_workspace_bytes(h, &need);
-  if (need > 0 && !workspace) return fail(PRISM_E_INVALID, "workspace is NULL");
-  if (workspace_bytes < need)
-    return fail(PRISM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-  hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// Workspace carve-up and the pass: Eq. 7 weights, fused pass, reductions, the
+// trilinear bias adjoint.  `adam` (optional) turns on the fused update of the
+// per-voxel parameters in the pass epilogue.
+int run_pass(const prism_problem* h, const float* y, const float* theta_micro, const float* theta_cal,
+             double* loss, float* grad_micro, float* grad_cal, void* workspace, uint32_t* status,
+             hipStream_t s, const PassArgs* adam) {
   char* ws = (char*)workspace;
   double* rec = (double*)ws;
   double* part = (double*)(ws + align256(h->ws_rec * sizeof(double)));
@@ -639,6 +636,17 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
   int32_t* counter = (int32_t*)(ws + align256(h->ws_rec * sizeof(double)) +
                                 align256(h->ws_part * sizeof(double)) + align256(h->ws_float * sizeof(float)));
   PassArgs a = pass_args(h, y, theta_micro, theta_cal, grad_micro, rec, wsp, status);
+  if (adam) {
+    a.adam = 1;
+    a.th_upd = adam->th_upd;
+    a.m_micro = adam->m_micro;
+    a.v_micro = adam->v_micro;
+    a.step = adam->step;
+    a.lr = adam->lr;
+    a.b1 = adam->b1;
+    a.b2 = adam->b2;
+    a.eps = adam->eps;
+  }
   hipError_t e = launch_stage(a, (int)h->groups.size(), s);
   if (e != hipSuccess) return hip_fail(e, "acquisition staging launch");
   if (!h->items.empty()) {
@@ -682,6 +690,75 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
   if (e != hipSuccess) return hip_fail(e, "reduction launch");
   e = launch_bias_trilinear(r, h->d_tri, (int)h->tri_groups.size(), s);
   if (e != hipSuccess) return hip_fail(e, "trilinear-bias launch");
+  return PRISM_OK;
+}
+
+int check_pass_args(const prism_problem* h, const float* y, const float* theta_micro, const float* theta_cal,
+                    const double* loss, const float* grad_micro, const float* grad_cal, const void* workspace,
+                    size_t workspace_bytes, const uint32_t* status) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  if ((h->n_y && !y) || (h->n_micro && (!theta_micro || !grad_micro)) || !theta_cal || !grad_cal ||
+      !loss || !status)
+    return fail(PRISM_E_INVALID, "NULL device pointer");
+  size_t need = 0;
+  prism_workspace_bytes(h, &need);
+  if (need > 0 && !workspace) return fail(PRISM_E_INVALID, "workspace is NULL");
+  if (workspace_bytes < need)
+    return fail(PRISM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+  return PRISM_OK;
+}
+
+}  // namespace
+
+int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* theta_micro,
+                        const float* theta_cal, double* loss, float* grad_micro, float* grad_cal,
+                        void* workspace, size_t workspace_bytes, uint32_t* status, void* stream) {
+  int rc = check_pass_args(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace,
+                           workspace_bytes, status);
+  if (rc != PRISM_OK) return rc;
+  return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status,
+                  (hipStream_t)stream, nullptr);
+}
+
+int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* theta_micro,
+                             float* theta_cal, float* m_micro, float* v_micro, float* m_cal,
+                             float* v_cal, int32_t* step, float lr, float beta1, float beta2,
+                             float eps, int32_t update_cal, double* loss, float* grad_micro,
+                             float* grad_cal, void* workspace, size_t workspace_bytes,
+                             uint32_t* status, void* stream) {
+  int rc = check_pass_args(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace,
+                           workspace_bytes, status);
+  if (rc != PRISM_OK) return rc;
+  if (!step || (h->n_micro && (!m_micro || !v_micro)) || (update_cal && (!m_cal || !v_cal)))
+    return fail(PRISM_E_INVALID, "NULL device pointer");
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+    return fail(PRISM_E_INVALID, "Adam hyper-parameters out of range");
+  hipStream_t s = (hipStream_t)stream;
+  bool fuse = true;  // the continuity prior reads neighbours' parameters during the pass
+  for (const GroupDev& g : h->groups)
+    if ((g.priors & PRISM_PRIOR_CONTINUITY) && g.nbh > 0) fuse = false;
+  if (fuse) {
+    PassArgs ad{};
+    ad.th_upd = theta_micro;
+    ad.m_micro = m_micro;
+    ad.v_micro = v_micro;
+    ad.step = step;
+    ad.lr = lr;
+    ad.b1 = beta1;
+    ad.b2 = beta2;
+    ad.eps = eps;
+    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad);
+    if (rc != PRISM_OK) return rc;
+  } else {
+    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, nullptr);
+    if (rc != PRISM_OK) return rc;
+    hipError_t e = launch_adam(theta_micro, grad_micro, m_micro, v_micro, h->n_micro, lr, beta1, beta2, eps,
+                               step, s, false);
+    if (e != hipSuccess) return hip_fail(e, "Adam launch");
+  }
+  hipError_t e = launch_adam(theta_cal, grad_cal, m_cal, v_cal, update_cal ? h->n_cal : 0, lr, beta1, beta2,
+                             eps, step, s, true);
+  if (e != hipSuccess) return hip_fail(e, "Adam launch");
   return PRISM_OK;
 }
 

@@ -11,6 +11,7 @@ constexpr int kBlock = 256;          // threads per block of the fused pass (4 w
 constexpr int kWave = 64;
 constexpr int kMaxK = 6;
 constexpr int kMaxC = kMaxK + 3;     // tissue compartments (csf, gm, wm_1..K, res)
+constexpr int kMaxCS = 12;           // kMaxC rounded up to a whole number of float4
 constexpr int kAcqStride = 12;       // floats per staged measurement
 constexpr int kRecHead = 19;         // record fields before alpha[N], beta[N]
 // record field indices (float64)
@@ -38,7 +39,7 @@ struct GroupDev {
   int64_t nbr_off;    // int32 offset of the neighbour table [ntab][V]; entries 0-5 are
                       // the face neighbours -x, +x, -y, +y, -z, +z, then the rest of 26
   int64_t ninv_off;   // float offset of 1/|N(x)| [V] (0 without neighbours)
-  int64_t w_off;      // float offset of the spatial weights [C][V] in the workspace
+  int64_t w_off;      // float offset of the spatial weights [V][cs] in the workspace
   int64_t glb_off;    // float offset of per-voxel dL/dlogB [V] in the workspace (trilinear)
   int64_t rec_off;    // float64 offset of the group's first item record
   int64_t grid_off;   // int32 offset of the dense raster->voxel index grid (trilinear)
@@ -46,6 +47,7 @@ struct GroupDev {
   int32_t V, N, K, C, P;
   int32_t mode, bias, n_bias, learn_d, nbh, priors;
   int32_t ntab;       // neighbour-table entries (nbh, or 6 for the bias TV alone)
+  int32_t cs;         // per-voxel stride of the interleaved fractions / weights (C rounded up to 4)
   int32_t nx, ny, nz;
   int32_t acq_off;    // offset of the group's measurements in the acquisition arrays
   int32_t rec_stride; // float64 fields per record
@@ -96,6 +98,14 @@ struct PassArgs {
   int32_t n_split;         // cross-wave buffer rows of the launch (max over items of rows*(WN-1))
   int32_t synth_only;      // forward model only (yhat written to g_micro as float [N][V])
   float* yhat;
+  // fused Adam (adam != 0): the epilogue updates theta_micro (th_upd, the same buffer as
+  // th_micro), m_micro and v_micro in place instead of storing the gradient
+  int32_t adam;
+  float* th_upd;
+  float* m_micro;
+  float* v_micro;
+  const int32_t* step;
+  float lr, b1, b2, eps;
 };
 
 struct ReduceArgs {
@@ -137,7 +147,8 @@ hipError_t launch_reduce(const ReduceArgs& a, int max_tile_fields, hipStream_t s
 hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups, int n_tri,
                                  hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
-                       float b1, float b2, float eps, int32_t* step, hipStream_t s);
+                       float b1, float b2, float eps, int32_t* step, hipStream_t s,
+                       bool advance = true);
 hipError_t launch_stitch(const StitchArgs& a, int K, int learn_d, hipStream_t s);
 hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n,
                         float em, float ep, float smin, float smax, hipStream_t s);

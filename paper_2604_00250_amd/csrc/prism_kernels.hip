@@ -421,6 +421,26 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
   }
 }
 
+// One Adam update (PyTorch's form) with step_size = lr / (1 - b1^t) and
+// ibc2 = 1 / sqrt(1 - b2^t); shared by k_adam and the fused pass so that both
+// give the same bits.
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float b1, float b2,
+                                         float eps, float step_size, float ibc2) {
+  m = fmaf(1.0f - b1, g - m, m);
+  v = fmaf(1.0f - b2, g * g, v * b2);
+  p = p - step_size * (m / fmaf(sqrtf(v), ibc2, eps));
+}
+
+// Adam's step-dependent factors for t = step[0] + 1, in float64 as k_adam takes them
+__device__ __forceinline__ void adam_factors(const int32_t* step, float lr, float b1, float b2,
+                                             float& step_size, float& ibc2) {
+  const int t = step[0] + 1;
+  const double bc1 = 1.0 - pow((double)b1, (double)t);
+  const double bc2 = 1.0 - pow((double)b2, (double)t);
+  step_size = (float)((double)lr / bc1);
+  ibc2 = (float)(1.0 / sqrt(bc2));
+}
+
 // statically sized LDS of the fused pass (one instance per kernel, shared by the
 // variants a persistent kernel inlines)
 constexpr int kRecVals = 18;  // per-thread record values of the fused pass
@@ -429,6 +449,7 @@ struct PassShared {
   double ep_d[2][kBlock];   // per-thread repulsion / sparsity partials
   float ep_f[4][kBlock];    // per-thread orphan / continuity / ordering / TV partials
   float ep_b[10][kBlock];   // per-thread quadratic-bias adjoint partials
+  float adam_sc[2];         // fused Adam: step size and 1/sqrt(1 - b2^t)
 };
 
 // The fused pass over one work item (a run of one group's voxels).
@@ -458,6 +479,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   const float4* acq_tab = acq;
 #endif
   for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
+  if (A.adam && tid == 0) adam_factors(A.step, A.lr, A.b1, A.b2, sh.adam_sc[0], sh.adam_sc[1]);
   __syncthreads();
 
   const int nb = (N * split) / WN, ne = (N * (split + 1)) / WN;
@@ -557,23 +579,38 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
           for (int a = 0; a < 3; ++a) gd[k][a] = sdata * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
         if (has_sp) {
-          const float* w = A.wsp + g.w_off;
+          // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weights interleaved [V][cs]
+          constexpr int C4 = (C + 3) / 4;
+          const float4* w4 = reinterpret_cast<const float4*>(A.wsp + g.w_off);
           const int32_t* nbr = A.nbr + g.nbr_off;
-          float sum[C];
+          float4 sum[C4];
 #pragma unroll
-          for (int c = 0; c < C; ++c) sum[c] = 0.0f;
+          for (int q = 0; q < C4; ++q) sum[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
           int cnt = 0;
           for (int q = 0; q < g.nbh; ++q) {
             const int u = nbr[(int64_t)q * V + v];
             if (u >= 0) {
               ++cnt;
 #pragma unroll
-              for (int c = 0; c < C; ++c) sum[c] += w[(int64_t)c * V + u];
+              for (int i = 0; i < C4; ++i) {
+                const float4 t = w4[(int64_t)u * C4 + i];
+                sum[i].x += t.x;
+                sum[i].y += t.y;
+                sum[i].z += t.z;
+                sum[i].w += t.w;
+              }
             }
           }
+          const float fc = (float)cnt;
 #pragma unroll
-          for (int c = 0; c < C; ++c)
-            gf[c] = fmaf(sc_sp, fmaf(w[(int64_t)c * V + v], (float)cnt, -sum[c]), gf[c]);
+          for (int i = 0; i < C4; ++i) {
+            const float4 t = w4[(int64_t)v * C4 + i];
+            const float own[4] = {t.x, t.y, t.z, t.w};
+            const float sm[4] = {sum[i].x, sum[i].y, sum[i].z, sum[i].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (4 * i + e < C) gf[4 * i + e] = fmaf(sc_sp, fmaf(own[e], fc, -sm[e]), gf[4 * i + e]);
+          }
         }
         if (g.priors & kPriorRep) {
           float lr = 0.0f;
@@ -691,10 +728,45 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           gout[row_dpar(C, K) + 1] = D.sig_dperp * sdata * acc[j].r[Acc<K, LD>::kDperp];
         }
         constexpr int P = 4 * K + 5 + (LD ? 2 : 0);
+        if (A.adam) {
+          // fused Adam on this voxel's parameters (only this thread touches them)
+          const float ss = sh.adam_sc[0], ib = sh.adam_sc[1];
+          float* th = A.th_upd + g.micro_off;
+          float* mm = A.m_micro + g.micro_off;
+          float* vv = A.v_micro + g.micro_off;
+          // in batches of kAdamBatch parameters: the batch's loads are issued
+          // together so that their latencies overlap, in few registers
+          constexpr int kAdamBatch = 8;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-          if (!isfinite(gout[p])) bad_grad = true;
-          gm[(int64_t)p * V + v] = gout[p];
+          for (int p0 = 0; p0 < P; p0 += kAdamBatch) {
+            float pp[kAdamBatch], m1[kAdamBatch], v1[kAdamBatch];
+#pragma unroll
+            for (int q = 0; q < kAdamBatch; ++q)
+              if (p0 + q < P) {
+                const int64_t i = (int64_t)(p0 + q) * V + v;
+                pp[q] = th[i];
+                m1[q] = mm[i];
+                v1[q] = vv[i];
+              }
+#pragma unroll
+            for (int q = 0; q < kAdamBatch; ++q)
+              if (p0 + q < P) {
+                const int p = p0 + q;
+                if (!isfinite(gout[p])) bad_grad = true;
+                const int64_t i = (int64_t)p * V + v;
+                adam_one(pp[q], gout[p], m1[q], v1[q], A.b1, A.b2, A.eps, ss, ib);
+                th[i] = pp[q];
+                mm[i] = m1[q];
+                vv[i] = v1[q];
+              }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        } else {
+#pragma unroll
+          for (int p = 0; p < P; ++p) {
+            if (!isfinite(gout[p])) bad_grad = true;
+            gm[(int64_t)p * V + v] = gout[p];
+          }
         }
         // bias-field adjoint dL/dlogB(x)
         float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
@@ -891,22 +963,25 @@ __device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, in
     if (c < C) f[c] *= inv;
 }
 
-// fractions f = softmax(logits) once per voxel, into the weight buffer
+// fractions f = softmax(logits) once per voxel, interleaved [V][cs] (padding 0)
 __global__ __launch_bounds__(kBlock) void k_fractions(PassArgs A) {
   const ItemDev it = A.items[blockIdx.x];
   const GroupDev g = A.groups[it.group];
   if (!((g.priors & kPriorSpatial) && g.nbh > 0)) return;
   const float* th = A.th_micro + g.micro_off;
   const int64_t V = g.V;
-  const int C = g.C;
-  float* f_out = A.wsp + g.w_off + (int64_t)C * V;
+  const int C = g.C, C4 = g.cs / 4;
+  float4* f_out = reinterpret_cast<float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
   for (int lv = threadIdx.x; lv < it.nv; lv += kBlock) {
     const int v = it.v0 + lv;
-    float f[kMaxC];
+    float f[kMaxCS];
     softmax_at(th, V, C, v, f);
 #pragma unroll
-    for (int c = 0; c < kMaxC; ++c)
-      if (c < C) f_out[(int64_t)c * V + v] = f[c];
+    for (int c = 0; c < kMaxCS; ++c)
+      if (c >= C) f[c] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kMaxCS / 4; ++i)
+      if (i < C4) f_out[(int64_t)v * C4 + i] = make_float4(f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
   }
 }
 
@@ -920,39 +995,57 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
   if ((g.priors & kPriorSpatial) && g.nbh > 0) {
     const int32_t* nbr = A.nbr + g.nbr_off;
     const int64_t V = g.V;
-    const int C = g.C;
-    const float* fr = A.wsp + g.w_off + (int64_t)C * V;
-    float* w_out = A.wsp + g.w_off;
+    const int C = g.C, C4 = g.cs / 4;
+    const float4* fr = reinterpret_cast<const float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
+    float4* w_out = reinterpret_cast<float4*>(A.wsp + g.w_off);
     const float delta = A.model.huber_delta;
     for (int lv = tid; lv < it.nv; lv += kBlock) {
       const int v = it.v0 + lv;
-      float mean[kMaxC];
+      float mean[kMaxCS];
 #pragma unroll
-      for (int c = 0; c < kMaxC; ++c) mean[c] = 0.0f;
+      for (int c = 0; c < kMaxCS; ++c) mean[c] = 0.0f;
       int cnt = 0;
       for (int q = 0; q < g.nbh; ++q) {
         const int u = nbr[(int64_t)q * V + v];
         if (u >= 0) {
           ++cnt;
 #pragma unroll
-          for (int c = 0; c < kMaxC; ++c)
-            if (c < C) mean[c] += fr[(int64_t)c * V + u];
+          for (int i = 0; i < kMaxCS / 4; ++i)
+            if (i < C4) {
+              const float4 t = fr[(int64_t)u * C4 + i];
+              mean[4 * i] += t.x;
+              mean[4 * i + 1] += t.y;
+              mean[4 * i + 2] += t.z;
+              mean[4 * i + 3] += t.w;
+            }
         }
       }
+      float own[kMaxCS];
+#pragma unroll
+      for (int i = 0; i < kMaxCS / 4; ++i)
+        if (i < C4) {
+          const float4 t = fr[(int64_t)v * C4 + i];
+          own[4 * i] = t.x;
+          own[4 * i + 1] = t.y;
+          own[4 * i + 2] = t.z;
+          own[4 * i + 3] = t.w;
+        }
       float ls = 0.0f;
       const float icnt = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
+      float w[kMaxCS];
 #pragma unroll
-      for (int c = 0; c < kMaxC; ++c)
-        if (c < C) {
-          float w = 0.0f;
-          if (cnt > 0) {
-            const float r = fr[(int64_t)c * V + v] - mean[c] * icnt;
-            const float ar = fabsf(r);
-            ls += ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta);
-            w = (ar <= delta ? r : copysignf(delta, r)) * icnt;
-          }
-          w_out[(int64_t)c * V + v] = w;
+      for (int c = 0; c < kMaxCS; ++c) {
+        w[c] = 0.0f;
+        if (c < C && cnt > 0) {
+          const float r = own[c] - mean[c] * icnt;
+          const float ar = fabsf(r);
+          ls += ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta);
+          w[c] = (ar <= delta ? r : copysignf(delta, r)) * icnt;
         }
+      }
+#pragma unroll
+      for (int i = 0; i < kMaxCS / 4; ++i)
+        if (i < C4) w_out[(int64_t)v * C4 + i] = make_float4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
       lsum += (double)ls;
     }
   }
@@ -1244,24 +1337,11 @@ __global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* t
 // Adam, PyTorch's form; t = step[0] + 1 is read by every block and the step
 // counter is advanced afterwards by k_step_advance (stream order), so no
 // block waits on another and no counter is contended.
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float b1, float b2,
-                                         float eps, float step_size, float ibc2) {
-  m = fmaf(1.0f - b1, g - m, m);
-  v = fmaf(1.0f - b2, g * g, v * b2);
-  p = p - step_size * (m / fmaf(sqrtf(v), ibc2, eps));
-}
-
 __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
                                               int64_t n, float lr, float b1, float b2, float eps,
                                               const int32_t* step, int vec4) {
   __shared__ float sc[2];
-  if (threadIdx.x == 0) {
-    const int t = step[0] + 1;
-    const double bc1 = 1.0 - pow((double)b1, (double)t);
-    const double bc2 = 1.0 - pow((double)b2, (double)t);
-    sc[0] = (float)((double)lr / bc1);
-    sc[1] = (float)(1.0 / sqrt(bc2));
-  }
+  if (threadIdx.x == 0) adam_factors(step, lr, b1, b2, sc[0], sc[1]);
   __syncthreads();
   const float step_size = sc[0], ibc2 = sc[1];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1431,7 +1511,7 @@ hipError_t launch_bias_trilinear(const ReduceArgs& a, const int32_t* tri_groups,
 }
 
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
-                       float b2, float eps, int32_t* step, hipStream_t s) {
+                       float b2, float eps, int32_t* step, hipStream_t s, bool advance) {
   const bool vec4 = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) |
                       reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
   int64_t blocks = (n + 2047) / 2048;
@@ -1441,7 +1521,7 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
                        eps, step, vec4 ? 1 : 0);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !advance) return e;
   hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
   return hipGetLastError();
 }

@@ -28,6 +28,7 @@ class Loop:
                  rprop=(0.5, 1.2, 1e-6, 50.0), calibrate: bool = True):
         self.st = state
         # calibrate=False keeps theta_cal fixed: the optimiser sees theta_micro only
+        self.calibrate = calibrate
         self.n_opt = state.n_micro + (state.n_cal if calibrate else 0)
         self.lr = lr
         self.optimizer = optimizer
@@ -44,10 +45,11 @@ class Loop:
             self.rstep = torch.full((n,), lr, dtype=torch.float32, device=dev)
             self.it = torch.zeros(1, dtype=torch.int64, device=dev)
 
-    def _record(self):
-        # history slot = completed optimiser steps (device counter), modulo the ring length
+    def _record(self, after_step=False):
+        # history slot = the iteration's index (device counter of completed steps,
+        # already advanced when the step ran first), modulo the ring length
         if self.optimizer == "adam":
-            idx = self.st.step[:1].to(torch.int64)
+            idx = self.st.step[:1].to(torch.int64) - (1 if after_step else 0)
         else:
             idx = self.it
         idx = torch.remainder(idx, self.hist_len)
@@ -55,16 +57,17 @@ class Loop:
 
     def step_eager(self):
         st = self.st
+        if self.optimizer == "adam":
+            # one call: loss at the current parameters, then the Adam step
+            st.iteration(self.lr, self.betas[0], self.betas[1], self.eps, update_cal=self.calibrate)
+            self._record(after_step=True)
+            return
         st.loss_grad()
         self._record()
-        if self.optimizer == "adam":
-            st.adam(self.lr, self.betas[0], self.betas[1], self.eps, n=self.n_opt)
-        else:
-            n = self.n_opt
-            em, ep, smin, smax = self.rprop
-            rprop_step_ptr(st.params.data_ptr(), st.grad.data_ptr(), self.prev.data_ptr(),
-                           self.rstep.data_ptr(), n, em, ep, smin, smax, st._s())
-            self.it.add_(1)
+        em, ep, smin, smax = self.rprop
+        rprop_step_ptr(st.params.data_ptr(), st.grad.data_ptr(), self.prev.data_ptr(),
+                       self.rstep.data_ptr(), self.n_opt, em, ep, smin, smax, st._s())
+        self.it.add_(1)
 
     def capture(self):
         """Capture one iteration; the library calls allocate nothing and never

@@ -165,6 +165,13 @@ class Problem:
         L.check(L.lib().prism_loss_grad(self.handle, y, th_micro, th_cal, loss, g_micro, g_cal, ws,
                                         ws_bytes, status, stream))
 
+    def iteration_adam_ptr(self, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal, step, lr, b1, b2, eps,
+                           update_cal, loss, g_micro, g_cal, ws, ws_bytes, status, stream):
+        L.check(L.lib().prism_iteration_adam(self.handle, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal,
+                                             step, float(lr), float(b1), float(b2), float(eps),
+                                             int(bool(update_cal)), loss, g_micro, g_cal, ws, ws_bytes,
+                                             status, stream))
+
     def synthesize_ptr(self, th_micro, th_cal, yhat, stream):
         L.check(L.lib().prism_synthesize(self.handle, th_micro, th_cal, yhat, stream))
 
@@ -275,7 +282,18 @@ class DeviceState:
         adam_step_ptr(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                       n, lr, beta1, beta2, eps, self.step.data_ptr(), self._s())
 
-    def iteration(self, lr=1e-2):
+    def iteration(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, update_cal=True):
+        """One Adam iteration through prism_iteration_adam (the per-voxel update
+        runs inside the fused pass); self.loss holds the loss before the step."""
+        pm, pc, gm, gc = self.ptrs()
+        m, v = self.m.data_ptr(), self.v.data_ptr()
+        self.prob.iteration_adam_ptr(self.y.data_ptr(), pm, pc, m, v, m + 4 * self.n_micro, v + 4 * self.n_micro,
+                                     self.step.data_ptr(), lr, beta1, beta2, eps, update_cal,
+                                     self.loss.data_ptr(), gm, gc, self.ws.data_ptr(), self.ws_bytes,
+                                     self.status.data_ptr(), self._s())
+
+    def iteration_unfused(self, lr=1e-2):
+        """The same iteration as prism_loss_grad followed by prism_adam_step."""
         self.loss_grad()
         self.adam(lr)
 

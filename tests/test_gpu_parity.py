@@ -182,3 +182,32 @@ def test_status_bits_for_zero_direction_and_nonfinite_data():
     y[3, 7] = np.nan
     r = run_gpu([dataclasses.replace(g, y=y)], [g.theta])
     assert r["status"] & 1 and r["status"] & 2
+    # NLL with an infinite noise level: the loss is not finite
+    gn = masked_group(shape=(4, 4, 4), K=2, mode="nll", seed=10, acq_kind="single33")
+    th = {k: v.copy() for k, v in gn.theta.items()}
+    th["sigma_log"] = np.array(np.inf, dtype=np.float32)
+    r = run_gpu([gn], [th])
+    assert r["status"] & 1
+    th["sigma_log"] = np.array(-np.inf, dtype=np.float32)
+    r = run_gpu([gn], [th])
+    assert r["status"] & 1
+
+
+def test_workspace_smaller_than_required_is_rejected():
+    import ctypes
+    import torch
+    from paper_2604_00250_amd import _lib as L
+    g = masked_group(shape=(5, 4, 3), K=2, mode="mse", seed=12, acq_kind="single33")
+    r = run_gpu([g], [g.theta])
+    st = r["state"]
+    need = st.prob.workspace_bytes()
+    assert need > 0
+    pm, pc, gm, gc = st.ptrs()
+    rc = L.lib().prism_loss_grad(st.prob.handle, st.y.data_ptr(), pm, pc, st.loss.data_ptr(), gm, gc,
+                                 st.ws.data_ptr(), need - 1, st.status.data_ptr(), None)
+    assert rc == L.PRISM_E_WORKSPACE
+    assert "workspace" in L.lib().prism_last_error().decode()
+    rc = L.lib().prism_loss_grad(st.prob.handle, st.y.data_ptr(), pm, pc, st.loss.data_ptr(), gm, gc,
+                                 None, need, st.status.data_ptr(), None)
+    assert rc == L.PRISM_E_INVALID
+    torch.cuda.synchronize()
