@@ -9,19 +9,31 @@ namespace prism {
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
-// hardware transcendentals: 2^x, log2(x), 1/x (about 1 ulp)
+// hardware transcendentals: 2^x, log2(x), 1/x, 1/sqrt(x), sqrt(x) (about 1 ulp)
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// numerically stable per-voxel transforms (prologue only; accuracy over speed)
+// e^x as 2^(x log2 e): two instructions, relative error a few ulp for |x| < 100
+__device__ __forceinline__ float exp_hw(float x) { return ex2(x * kLog2e); }
+
+// log(1 + e) for e >= 0 without cancellation: log2(w) ln2 * e / (w - 1), w = 1 + e
+// (the second factor corrects the rounding of w; w == 1 means log1p(e) = e)
+__device__ __forceinline__ float log1p_hw(float e) {
+  const float w = 1.0f + e;
+  return w == 1.0f ? e : lg2(w) * kLn2 * (e * rcp(w - 1.0f));
+}
+
+// numerically stable per-voxel transforms
 __device__ __forceinline__ float softplus_f(float x) {
-  return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)));
+  return fmaxf(x, 0.0f) + log1p_hw(exp_hw(-fabsf(x)));
 }
 __device__ __forceinline__ float sigmoid_f(float x) {
   // 1 / (1 + e^-x) without overflow for large |x|
-  const float e = expf(-fabsf(x));
-  const float s = 1.0f / (1.0f + e);
+  const float e = exp_hw(-fabsf(x));
+  const float s = rcp(1.0f + e);
   return x >= 0.0f ? s : e * s;
 }
 

@@ -183,10 +183,10 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
   float sum = 0.0f;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    lg[c] = expf(lg[c] - m);
+    lg[c] = exp_hw(lg[c] - m);
     sum += lg[c];
   }
-  const float inv = 1.0f / sum;
+  const float inv = rcp(sum);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     dv.f[c] = lg[c] * inv;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     const float n2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
     float in = 0.0f;
     if (n2 > 0.0f) {
-      in = 1.0f / sqrtf(n2);
+      in = rsq(n2);
     } else {
       zero_dir = true;
     }
@@ -225,7 +225,7 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     dv.sig_dperp = 0.0f;
   }
   const float* cal = A.th_cal + g.cal_off;
-  x.B = expf(log_bias(g, cal, A.coords[g.vox_off + v]));
+  x.B = exp_hw(log_bias(g, cal, A.coords[g.vox_off + v]));
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +428,7 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
                                          float eps, float step_size, float ibc2) {
   m = fmaf(1.0f - b1, g - m, m);
   v = fmaf(1.0f - b2, g * g, v * b2);
-  p = p - step_size * (m / fmaf(sqrtf(v), ibc2, eps));
+  p = p - step_size * (m * rcp(fmaf(sqrt_hw(v), ibc2, eps)));
 }
 
 // Adam's step-dependent factors for t = step[0] + 1, in float64 as k_adam takes them
@@ -695,7 +695,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
               const float uy = th[(int64_t)row_v(C, k, 1) * V + u];
               const float uz = th[(int64_t)row_v(C, k, 2) * V + u];
               const float n2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-              const float in = n2 > 0.0f ? 1.0f / sqrtf(n2) : 0.0f;
+              const float in = n2 > 0.0f ? rsq(n2) : 0.0f;
               const float dx = ux * in, dy = uy * in, dz = uz * in;
               const float dot = x[j].d[k][0] * dx + x[j].d[k][1] * dy + x[j].d[k][2] * dz;
               lc = fmaf(ax, fmaf(-dot, dot, 1.0f), lc);
@@ -954,10 +954,10 @@ __device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, in
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c)
     if (c < C) {
-      f[c] = expf(f[c] - m);
+      f[c] = exp_hw(f[c] - m);
       s += f[c];
     }
-  const float inv = 1.0f / s;
+  const float inv = rcp(s);
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c)
     if (c < C) f[c] *= inv;
