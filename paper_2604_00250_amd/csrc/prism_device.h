@@ -37,6 +37,17 @@ __device__ __forceinline__ float sigmoid_f(float x) {
   return x >= 0.0f ? s : e * s;
 }
 
+// One float of a row of `nbytes` bytes at byte offset `off`, through a buffer
+// descriptor: the row's base stays in scalar registers and the lane supplies
+// only a 32-bit offset (no per-lane 64-bit address arithmetic).  Offsets at or
+// beyond nbytes read 0.  Word 3 is the gfx9-family raw 32-bit buffer format.
+__device__ __forceinline__ float load_row_f32(const float* row, uint32_t nbytes, uint32_t off) {
+  __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(row), (short)0, (int)nbytes, 0x00020000);
+  // the builtin returns the 32 loaded bits; reinterpret them, do not convert them
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // ---------------------------------------------------------------------------
 // wave reductions
 // ---------------------------------------------------------------------------

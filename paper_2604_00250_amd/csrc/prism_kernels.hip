@@ -232,7 +232,7 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
 // one (voxel, measurement) pair: forward, data term, adjoint accumulation
 // ---------------------------------------------------------------------------
 template <int K, int MODE, bool LD>
-__device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv,
+__device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv, float valid,
                                      const float4 a, const float4 b, const float4 c, float inv_s2,
                                      float& t_loss, float& t_sig, float& sq, float& seed) {
   const float gx = a.x, gy = a.y, gz = a.z;
@@ -255,8 +255,10 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   const float AB = c.x * x.B;
   const float q = AB * S;                 // yhat - beta
   const float yh = q + c.y;               // Eq. 6
+  // valid (0 for lanes past the end of the item) zeroes the lane's residual, so
+  // the loss, the per-measurement sums and the (unstored) adjoint all drop it
   if (MODE == kMSE) {
-    const float r = yh - yv;
+    const float r = (yh - yv) * valid;
     seed = r;
     t_loss = r * r;
     t_sig = 0.0f;
@@ -266,9 +268,9 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
     float omr;
     const float li = log_i0e(z, omr);
     const float dd = ah - ay;
-    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li);
-    t_sig = fmaf(dd * dd, inv_s2, 2.0f * z * omr);
-    const float sd = fmaf(ay, omr, dd) * inv_s2;
+    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li) * valid;
+    t_sig = fmaf(dd * dd, inv_s2, 2.0f * z * omr) * valid;
+    const float sd = fmaf(ay, omr, dd) * inv_s2 * valid;
     seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
   }
   sq = seed * q;
@@ -321,17 +323,19 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
                                                  int nb, int ne, int N, float inv_s2, int lane,
                                                  float* wacc, double& dloss, double& dsig) {
   const int lane16 = lane & 15;
-  const float* yp[VL];
+  uint32_t voff[VL];  // byte offsets of the lane's voxels in a row of y
 #pragma unroll
-  for (int j = 0; j < VL; ++j) yp[j] = yg + vox[j];
+  for (int j = 0; j < VL; ++j) voff[j] = (uint32_t)vox[j] * 4u;
+  const uint32_t rowb = (uint32_t)V * 4u;  // bytes in a row of y (V <= 1023^3)
   // y prefetch ring kPf measurements deep (slot u holds measurement nb + u mod kPf)
   float yr[kPf][VL];
 #pragma unroll
   for (int u = 0; u < kPf; ++u)
 #pragma unroll
-    for (int j = 0; j < VL; ++j) yr[u][j] = yp[j][(int64_t)min(nb + u, ne - 1) * V];
+    for (int j = 0; j < VL; ++j) yr[u][j] = load_row_f32(yg + (int64_t)min(nb + u, ne - 1) * V, rowb, voff[j]);
   v4f Da, Db;
   float lacc, sacc;
+  float sel;  // one-hot over the 16 lanes of a row: 1 at lane16 == t (column t of the tile)
   int n0 = nb;
   // one measurement: the ring slot u is refilled (measurement n + kPf) only after
   // its value has been consumed, so the load can target the slot's register
@@ -345,23 +349,26 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll
     for (int j = 0; j < VL; ++j) {
       float tl, ts, sq, sd;
-      pair<K, MODE, LD>(x[j], acc[j], slot[j], a, b, c, inv_s2, tl, ts, sq, sd);
-      lacc = fmaf(valid[j], tl, lacc);
-      if (MODE == kNLL) sacc = fmaf(valid[j], ts, sacc);
-      pa = fmaf(valid[j], sq, pa);
-      pb = fmaf(valid[j], sd, pb);
+      pair<K, MODE, LD>(x[j], acc[j], slot[j], valid[j], a, b, c, inv_s2, tl, ts, sq, sd);
+      lacc += tl;
+      if (MODE == kNLL) sacc += ts;
+      pa = j == 0 ? sq : pa + sq;
+      pb = j == 0 ? sd : pb + sd;
     }
+    // refill from the measurement's row (a uniform base) at the lane's voxel
+    const float* row = yg + (int64_t)min(n + kPf, ne - 1) * V;  // clamped: in bounds
 #pragma unroll
-    for (int j = 0; j < VL; ++j) slot[j] = yp[j][(int64_t)min(n + kPf, ne - 1) * V];  // clamped: in bounds
-    const float sel = lane16 == t ? 1.0f : 0.0f;
+    for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
     Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
     Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+    sel = dpp_f32<0x111>(sel);  // row_shr:1 moves the one to lane16 == t + 1
   };
   auto tile_begin = [&]() {
     Da = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     Db = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     lacc = 0.0f;
     sacc = 0.0f;
+    sel = lane16 == 0 ? 1.0f : 0.0f;
   };
   // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
   auto group = [&](int t0) {
