@@ -34,9 +34,17 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autograd; %VALU"
 
 # Algorithmic work of one (voxel, measurement) pair of the fused pass at K = 3,
-# MSE, fixed diffusivities (counted from the pass's arithmetic, FMA = 1):
-#   forward 10K + 8 VALU and 2K exps, adjoint 12K + 10 VALU -> 84 VALU + 6 exp.
-ALG_VALU_PER_PAIR = 84
+# MSE, fixed diffusivities: every operation of Eq. 3-6, the data term and the
+# adjoint counted once, an FMA as one, fused wherever the algebra allows:
+#   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2,
+#     f_intra mix 1, product 1, accumulate 1 (9K); calibration 3    -> 9K + 6
+#   data term: residual 1, squared-residual accumulate 1                  -> 2
+#   adjoint: seed*q 1 and its accumulate 1, dS 1, isotropic 3, shared
+#     Q2(1-f_intra) 1; per fibre fraction 1, dE 1, e1(1-e2) 1, f_intra 1,
+#     P2 h 1, bracket 1, cos e1 1, dE*cos e1 1, *bracket 1, direction 3 (12K)
+#                                                                   -> 12K + 7
+#   total 21K + 15 = 78 VALU and 2K = 6 exps.
+ALG_VALU_PER_PAIR = 78
 ALG_EXP_PER_PAIR = 6
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam
