@@ -1344,9 +1344,11 @@ __global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* t
 // Adam, PyTorch's form; t = step[0] + 1 is read by every block and the step
 // counter is advanced afterwards by k_step_advance (stream order), so no
 // block waits on another and no counter is contended.
+// With advance != 0 the launch is a single block, which advances the step
+// counter itself once every thread has used it.
 __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v,
                                               int64_t n, float lr, float b1, float b2, float eps,
-                                              const int32_t* step, int vec4) {
+                                              int32_t* step, int vec4, int advance) {
   __shared__ float sc[2];
   if (threadIdx.x == 0) adam_factors(step, lr, b1, b2, sc[0], sc[1]);
   __syncthreads();
@@ -1379,6 +1381,13 @@ __global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m
     p[i] = pp;
     m[i] = mm;
     v[i] = vv;
+  }
+  if (advance) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      step[0] = step[0] + 1;
+      step[1] = 0;
+    }
   }
 }
 
@@ -1524,11 +1533,13 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   int64_t blocks = (n + 2047) / 2048;
   if (blocks < 1) blocks = 1;
   if (blocks > 4096) blocks = 4096;
-  if (n > 0)
+  // a one-block update advances the counter itself (one launch instead of two)
+  const int self_advance = advance && blocks == 1 ? 1 : 0;
+  if (n > 0 || self_advance)
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
-                       eps, step, vec4 ? 1 : 0);
+                       eps, step, vec4 ? 1 : 0, self_advance);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !advance) return e;
+  if (e != hipSuccess || !advance || self_advance) return e;
   hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step);
   return hipGetLastError();
 }
