@@ -48,6 +48,17 @@ __device__ __forceinline__ float load_row_f32(const float* row, uint32_t nbytes,
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// Work item of block b in a launch of n blocks.  The dispatcher deals blocks
+// to the 8 XCDs in turn (block b to XCD b mod 8) and each XCD has its own L2;
+// giving XCD x one contiguous run of items keeps the neighbours that an item
+// gathers (the next row and slice of the volume) in the L2 that serves it.
+// A bijection of [0, n).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + (x < r ? x : r) + b / kXcd;
+}
+
 // ---------------------------------------------------------------------------
 // wave reductions
 // ---------------------------------------------------------------------------

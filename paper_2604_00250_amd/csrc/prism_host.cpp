@@ -66,6 +66,7 @@ struct prism_problem {
   std::vector<int32_t> tri_groups;
   std::vector<int32_t> acq_off;
   int max_field_chunks = 0;
+  int spatial_cs = 0;  // widest [V][cs] row of the groups with the Eq. 7 prior
   int persistent_grid = 0;
   int64_t n_vox = 0, n_micro = 0, n_cal = 0, n_y = 0;
   size_t ws_rec = 0, ws_part = 0, ws_float = 0;  // element counts
@@ -459,7 +460,10 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
     g.cs = (g.C + 3) & ~3;
     wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned rows
     g.w_off = wfl;  // [V][cs] residual weights, then [V][cs] fractions
-    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) wfl += 2 * (int64_t)g.cs * V;
+    if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) {
+      wfl += 2 * (int64_t)g.cs * V;
+      h->spatial_cs = std::max(h->spatial_cs, g.cs);
+    }
     g.glb_off = wfl;
     if (d.bias == PRISM_BIAS_TRILINEAR8) wfl += V;
     wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned acquisition table
@@ -652,7 +656,7 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
   if (!h->items.empty()) {
     a.item_base = 0;
     a.n_items = (int)h->items.size();
-    e = launch_spatial(a, (int)h->items.size(), s);
+    e = launch_spatial(a, (int)h->items.size(), h->spatial_cs, s);
     if (e != hipSuccess) return hip_fail(e, "spatial-prior launch");
   }
   for (const Bucket& b : h->buckets) {

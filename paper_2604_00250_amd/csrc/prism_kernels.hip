@@ -5,7 +5,8 @@
 //             voxels); lane = voxel, loop over measurements with the
 //             acquisition staged in LDS; exps are recomputed, never stored.
 // k_synth     forward model only (yhat).
-// k_spatial   Eq. 7 residual weights rho'(r)/|N| per voxel and compartment.
+// k_fractions, k_spatial  Eq. 7: softmax fractions, then the residual weights
+//             rho'(r)/|N| per voxel and compartment.
 // k_reduce1/2 deterministic two-stage reduction of per-item records into the
 //             calibration gradient and the loss terms.
 // k_bias_tri  gradient of the 8^3 trilinear log-bias grid.
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
     PassArgs A, const float4* __restrict__ acq_global) {
   extern __shared__ float4 smem4[];
   __shared__ PassShared sh;
-  const ItemDev it = A.items[A.item_base + blockIdx.x];
+  const ItemDev it = A.items[A.item_base + xcd_item(blockIdx.x, gridDim.x)];
   pass_item<K, MODE, LD, VL>(A, acq_global, it, smem4, sh);
 }
 
@@ -970,16 +971,21 @@ __device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, in
     if (c < C) f[c] *= inv;
 }
 
+// The two Eq. 7 kernels run one voxel per thread with kAuxBlock threads per
+// work item: with fewer threads each one walked several voxels and the
+// dependent table-then-gather loads of each voxel in turn.
+constexpr int kAuxBlock = 512;
+
 // fractions f = softmax(logits) once per voxel, interleaved [V][cs] (padding 0)
-__global__ __launch_bounds__(kBlock) void k_fractions(PassArgs A) {
-  const ItemDev it = A.items[blockIdx.x];
+__global__ __launch_bounds__(kAuxBlock) void k_fractions(PassArgs A) {
+  const ItemDev it = A.items[xcd_item(blockIdx.x, gridDim.x)];
   const GroupDev g = A.groups[it.group];
   if (!((g.priors & kPriorSpatial) && g.nbh > 0)) return;
   const float* th = A.th_micro + g.micro_off;
   const int64_t V = g.V;
   const int C = g.C, C4 = g.cs / 4;
   float4* f_out = reinterpret_cast<float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
-  for (int lv = threadIdx.x; lv < it.nv; lv += kBlock) {
+  for (int lv = threadIdx.x; lv < it.nv; lv += kAuxBlock) {
     const int v = it.v0 + lv;
     float f[kMaxCS];
     softmax_at(th, V, C, v, f);
@@ -992,10 +998,16 @@ __global__ __launch_bounds__(kBlock) void k_fractions(PassArgs A) {
   }
 }
 
-// Eq. 7 residual weights w_c(x) = rho'(r_c(x)) / |N(x)| from the stored fractions
-__global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
-  __shared__ double red[4];
-  const ItemDev it = A.items[blockIdx.x];
+// Eq. 7 residual weights w_c(x) = rho'(r_c(x)) / |N(x)| from the stored fractions.
+// Neighbours are taken six at a time: all six table entries are loaded, then
+// all their fraction rows (an absent neighbour reads the voxel's own row with
+// weight 0), so one round trip serves six neighbours.  C4M bounds the float4
+// columns of the rows (the launch takes the widest of the problem's groups).
+template <int C4M>
+__global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
+  constexpr int kNb = 6;
+  __shared__ double red[kAuxBlock / 64];
+  const ItemDev it = A.items[xcd_item(blockIdx.x, gridDim.x)];
   const GroupDev g = A.groups[it.group];
   const int tid = threadIdx.x;
   double lsum = 0.0;
@@ -1006,30 +1018,41 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
     const float4* fr = reinterpret_cast<const float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
     float4* w_out = reinterpret_cast<float4*>(A.wsp + g.w_off);
     const float delta = A.model.huber_delta;
-    for (int lv = tid; lv < it.nv; lv += kBlock) {
+    for (int lv = tid; lv < it.nv; lv += kAuxBlock) {
       const int v = it.v0 + lv;
-      float mean[kMaxCS];
+      float mean[4 * C4M];
 #pragma unroll
-      for (int c = 0; c < kMaxCS; ++c) mean[c] = 0.0f;
+      for (int c = 0; c < 4 * C4M; ++c) mean[c] = 0.0f;
       int cnt = 0;
-      for (int q = 0; q < g.nbh; ++q) {
-        const int u = nbr[(int64_t)q * V + v];
-        if (u >= 0) {
-          ++cnt;
+      for (int q0 = 0; q0 < g.nbh; q0 += kNb) {
+        int u[kNb];
 #pragma unroll
-          for (int i = 0; i < kMaxCS / 4; ++i)
+        for (int j = 0; j < kNb; ++j) u[j] = q0 + j < g.nbh ? nbr[(int64_t)(q0 + j) * V + v] : -1;
+        float4 t[kNb][C4M];
+#pragma unroll
+        for (int j = 0; j < kNb; ++j) {
+          const int64_t src = (int64_t)(u[j] >= 0 ? u[j] : v) * C4;
+#pragma unroll
+          for (int i = 0; i < C4M; ++i)
+            if (i < C4) t[j][i] = fr[src + i];
+        }
+#pragma unroll
+        for (int j = 0; j < kNb; ++j) {
+          const float on = u[j] >= 0 ? 1.0f : 0.0f;
+          cnt += u[j] >= 0 ? 1 : 0;
+#pragma unroll
+          for (int i = 0; i < C4M; ++i)
             if (i < C4) {
-              const float4 t = fr[(int64_t)u * C4 + i];
-              mean[4 * i] += t.x;
-              mean[4 * i + 1] += t.y;
-              mean[4 * i + 2] += t.z;
-              mean[4 * i + 3] += t.w;
+              mean[4 * i] = fmaf(on, t[j][i].x, mean[4 * i]);
+              mean[4 * i + 1] = fmaf(on, t[j][i].y, mean[4 * i + 1]);
+              mean[4 * i + 2] = fmaf(on, t[j][i].z, mean[4 * i + 2]);
+              mean[4 * i + 3] = fmaf(on, t[j][i].w, mean[4 * i + 3]);
             }
         }
       }
-      float own[kMaxCS];
+      float own[4 * C4M];
 #pragma unroll
-      for (int i = 0; i < kMaxCS / 4; ++i)
+      for (int i = 0; i < C4M; ++i)
         if (i < C4) {
           const float4 t = fr[(int64_t)v * C4 + i];
           own[4 * i] = t.x;
@@ -1039,9 +1062,9 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
         }
       float ls = 0.0f;
       const float icnt = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
-      float w[kMaxCS];
+      float w[4 * C4M];
 #pragma unroll
-      for (int c = 0; c < kMaxCS; ++c) {
+      for (int c = 0; c < 4 * C4M; ++c) {
         w[c] = 0.0f;
         if (c < C && cnt > 0) {
           const float r = own[c] - mean[c] * icnt;
@@ -1051,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
         }
       }
 #pragma unroll
-      for (int i = 0; i < kMaxCS / 4; ++i)
+      for (int i = 0; i < C4M; ++i)
         if (i < C4) w_out[(int64_t)v * C4 + i] = make_float4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
       lsum += (double)ls;
     }
@@ -1059,8 +1082,12 @@ __global__ __launch_bounds__(kBlock) void k_spatial(PassArgs A) {
   lsum = wave_sum_f64(lsum);
   if ((tid & 63) == 0) red[tid >> 6] = lsum;
   __syncthreads();
-  if (tid == 0)
-    A.rec[g.rec_off + (int64_t)it.rec * g.rec_stride + kRecSpatial] = red[0] + red[1] + red[2] + red[3];
+  if (tid == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kAuxBlock / 64; ++i) s += red[i];
+    A.rec[g.rec_off + (int64_t)it.rec * g.rec_stride + kRecSpatial] = s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1501,12 +1528,18 @@ hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_spatial(const PassArgs& a, int n_items, hipStream_t s) {
+hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fractions, dim3(n_items), dim3(kBlock), 0, s, a);
+  // k_spatial also writes each item's (zero) record when no group has the prior
+  hipLaunchKernelGGL(k_fractions, dim3(n_items), dim3(kAuxBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_spatial, dim3(n_items), dim3(kBlock), 0, s, a);
+  if (max_cs <= 4)
+    hipLaunchKernelGGL(k_spatial<1>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+  else if (max_cs <= 8)
+    hipLaunchKernelGGL(k_spatial<2>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_spatial<kMaxCS / 4>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
   return hipGetLastError();
 }
 
