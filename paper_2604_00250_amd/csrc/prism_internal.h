@@ -137,7 +137,8 @@ struct StitchArgs {
 
 // launchers (prism_kernels.hip)
 // max_cs: largest interleaved row width (cs) of the groups with the Eq. 7 prior, 0 if none
-hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, hipStream_t s);
+// max_nv: voxels of the largest work item
+hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, int max_nv, hipStream_t s);
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
                                   hipStream_t s);

@@ -971,9 +971,10 @@ __device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, in
     if (c < C) f[c] *= inv;
 }
 
-// The two Eq. 7 kernels run one voxel per thread with kAuxBlock threads per
-// work item: with fewer threads each one walked several voxels and the
-// dependent table-then-gather loads of each voxel in turn.
+// The two Eq. 7 kernels run one block per work item with up to kAuxBlock
+// threads, one voxel per thread (the launch sizes the block to the largest
+// item): with fewer threads each one walked several voxels and the dependent
+// table-then-gather loads of each voxel in turn.
 constexpr int kAuxBlock = 512;
 
 // fractions f = softmax(logits) once per voxel, interleaved [V][cs] (padding 0)
@@ -985,7 +986,7 @@ __global__ __launch_bounds__(kAuxBlock) void k_fractions(PassArgs A) {
   const int64_t V = g.V;
   const int C = g.C, C4 = g.cs / 4;
   float4* f_out = reinterpret_cast<float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
-  for (int lv = threadIdx.x; lv < it.nv; lv += kAuxBlock) {
+  for (int lv = threadIdx.x; lv < it.nv; lv += blockDim.x) {
     const int v = it.v0 + lv;
     float f[kMaxCS];
     softmax_at(th, V, C, v, f);
@@ -1018,7 +1019,7 @@ __global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
     const float4* fr = reinterpret_cast<const float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
     float4* w_out = reinterpret_cast<float4*>(A.wsp + g.w_off);
     const float delta = A.model.huber_delta;
-    for (int lv = tid; lv < it.nv; lv += kAuxBlock) {
+    for (int lv = tid; lv < it.nv; lv += blockDim.x) {
       const int v = it.v0 + lv;
       float mean[4 * C4M];
 #pragma unroll
@@ -1084,8 +1085,7 @@ __global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kAuxBlock / 64; ++i) s += red[i];
+    for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += red[i];
     A.rec[g.rec_off + (int64_t)it.rec * g.rec_stride + kRecSpatial] = s;
   }
 }
@@ -1528,18 +1528,20 @@ hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, hipStream_t s) {
+hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, int max_nv, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
+  // whole waves, one thread per voxel of the largest item, at most kAuxBlock
+  const dim3 grid(n_items), block(std::min(kAuxBlock, std::max(64, (max_nv + 63) / 64 * 64)));
   // k_spatial also writes each item's (zero) record when no group has the prior
-  hipLaunchKernelGGL(k_fractions, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+  hipLaunchKernelGGL(k_fractions, grid, block, 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (max_cs <= 4)
-    hipLaunchKernelGGL(k_spatial<1>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+    hipLaunchKernelGGL(k_spatial<1>, grid, block, 0, s, a);
   else if (max_cs <= 8)
-    hipLaunchKernelGGL(k_spatial<2>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+    hipLaunchKernelGGL(k_spatial<2>, grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL(k_spatial<kMaxCS / 4>, dim3(n_items), dim3(kAuxBlock), 0, s, a);
+    hipLaunchKernelGGL(k_spatial<kMaxCS / 4>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 
