@@ -35,16 +35,18 @@ METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autogr
 
 # Algorithmic work of one (voxel, measurement) pair of the fused pass at K = 3,
 # MSE, fixed diffusivities: every operation of Eq. 3-6, the data term and the
-# adjoint counted once, an FMA as one, fused wherever the algebra allows:
+# adjoint counted once, an FMA as one, fused wherever the algebra allows
+# (per-voxel factors such as the bias field and each fibre's fraction are
+# applied once per voxel, outside the per-pair work):
 #   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2,
-#     f_intra mix 1, product 1, accumulate 1 (9K); calibration 3    -> 9K + 6
+#     f_intra mix 1, product 1, accumulate 1 (9K); gain and offset 2 -> 9K + 5
 #   data term: residual 1, squared-residual accumulate 1                  -> 2
-#   adjoint: seed*q 1 and its accumulate 1, dS 1, isotropic 3, shared
-#     Q2(1-f_intra) 1; per fibre fraction 1, dE 1, e1(1-e2) 1, f_intra 1,
-#     P2 h 1, bracket 1, cos e1 1, dE*cos e1 1, *bracket 1, direction 3 (12K)
-#                                                                   -> 12K + 7
-#   total 21K + 15 = 78 VALU and 2K = 6 exps.
-ALG_VALU_PER_PAIR = 78
+#   adjoint: seed*q 1 and its accumulate 1, dS 1, dS(-2b) 1, isotropic 3,
+#     f_intra accumulate 1; per fibre fraction 1, e1 e2 1, e1(1-e2) 1,
+#     f_intra sum 1, bracket 1, cos e1 1, *bracket 1, *dS(-2b) 1,
+#     direction 3 (11K)                                               -> 11K + 8
+#   total 20K + 15 = 75 VALU and 2K = 6 exps.
+ALG_VALU_PER_PAIR = 75
 ALG_EXP_PER_PAIR = 6
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam

@@ -66,7 +66,7 @@ __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* 
     acq[3 * n + 0] = make_float4(gv[0], gv[1], gv[2], -b * dpar * kLog2e);
     acq[3 * n + 1] = make_float4(-b * dperp * kLog2e, expf(-b * A.model.d_csf),
                                  expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
-    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b * dpar, 2.0f * b * dperp);
+    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b, 0.0f);
   }
 }
 
@@ -82,10 +82,10 @@ __global__ __launch_bounds__(256) void k_stage(PassArgs A) {
 // ---------------------------------------------------------------------------
 template <int K, bool LD>
 struct Vox {
-  float F[K + 3];   // S0 * fraction, order csf, gm, wm_0..wm_{K-1}, res
+  float F[K + 3];   // B S0 * fraction (bias field folded in), order csf, gm, wm_0..wm_{K-1}, res
   float d[K][3];    // unit directions
   float fin, omf;   // f_intra, 1 - f_intra
-  float B;          // bias field
+  float dpq, dqfin; // Dpar - Dperp, Dperp f_intra (the fibre-angle adjoint)
   float dpar, dperp;
 };
 
@@ -93,13 +93,13 @@ struct Vox {
 template <int K, bool LD>
 struct Acc {
   static constexpr int C = K + 3;
-  static constexpr int kGd = C;               // sum_n dc_k g_n      (dL/dd_k), 3K
+  static constexpr int kGd = C;               // sum_n dc_k g_n / F_k (dL/dd_k / F_k), 3K
   static constexpr int kFin = C + 3 * K;      // sum_n sum_k dE_k e1 (1 - e2)
   static constexpr int kLogB = C + 3 * K + 1; // sum_n seed (yhat - beta)
   static constexpr int kDpar = C + 3 * K + 2; // learned diffusivities
   static constexpr int kDperp = C + 3 * K + 3;
   static constexpr int N = C + 3 * K + 2 + (LD ? 2 : 0);
-  float r[N];                                 // r[c] = sum_n dS E_c (dL/dF_c)
+  float r[N];                                 // r[c] = sum_n dS E_c (dL/dF_c / B)
 };
 
 // raw parameter rows of theta_micro [P][V]
@@ -113,6 +113,7 @@ struct Derived {            // quantities the epilogue needs again
   float f[kMaxC];
   float invn[kMaxK];
   float sig_dpar, sig_dperp;
+  float B;                  // bias field
 };
 
 __device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, int32_t pc) {
@@ -188,10 +189,13 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     sum += lg[c];
   }
   const float inv = rcp(sum);
+  const float* cal = A.th_cal + g.cal_off;
+  dv.B = exp_hw(log_bias(g, cal, A.coords[g.vox_off + v]));
+  const float BS0 = dv.B * dv.S0;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     dv.f[c] = lg[c] * inv;
-    x.F[c] = dv.S0 * dv.f[c];
+    x.F[c] = BS0 * dv.f[c];
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -225,8 +229,9 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     dv.sig_dpar = 0.0f;
     dv.sig_dperp = 0.0f;
   }
-  const float* cal = A.th_cal + g.cal_off;
-  x.B = exp_hw(log_bias(g, cal, A.coords[g.vox_off + v]));
+  const float dperp = LD ? x.dperp : A.model.d_perp;
+  x.dpq = (LD ? x.dpar : A.model.d_par) - dperp;
+  x.dqfin = dperp * x.fin;
 }
 
 // ---------------------------------------------------------------------------
@@ -253,8 +258,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
     E[k] = e1[k] * h[k];                  // Eq. 5
     S = fmaf(x.F[2 + k], E[k], S);        // Eq. 3
   }
-  const float AB = c.x * x.B;
-  const float q = AB * S;                 // yhat - beta
+  const float q = c.x * S;                // yhat - beta (B is in F)
   const float yh = q + c.y;               // Eq. 6
   // valid (0 for lanes past the end of the item) zeroes the lane's residual, so
   // the loss, the per-measurement sums and the (unstored) adjoint all drop it
@@ -276,27 +280,28 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   }
   sq = seed * q;
   acc.r[Acc<K, LD>::kLogB] += sq;
-  const float dS = seed * AB;
-  // Q2 (1 - f_intra), shared by the K fibres
-  const float q2o = (LD ? c.w * x.dperp : c.w) * x.omf;
+  // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of fibre c's signal
+  const float dS = seed * c.x;
+  const float dSz = dS * c.z;             // dS (-2b), the factor of dE/dcos shared by the fibres
   acc.r[0] = fmaf(dS, b.y, acc.r[0]);
   acc.r[1] = fmaf(dS, b.z, acc.r[1]);
   acc.r[K + 2] = fmaf(dS, b.w, acc.r[K + 2]);
+  float gfin = 0.0f;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     acc.r[2 + k] = fmaf(dS, E[k], acc.r[2 + k]);
-    const float dE = dS * x.F[2 + k];
     const float e12 = e1[k] * e2[k];
-    acc.r[Acc<K, LD>::kFin] = fmaf(dE, e1[k] - e12, acc.r[Acc<K, LD>::kFin]);
-    const float p2 = LD ? c.z * x.dpar : c.z;
-    // dE/dcos = cos e1 (P2 h + Q2 (1-fin) e2)
-    const float t = fmaf(q2o, e2[k], p2 * h[k]);
-    const float dc = dE * (cc[k] * e1[k]) * t;
+    gfin = fmaf(x.F[2 + k], e1[k] - e12, gfin);   // sum_k F_k dE_k/df_intra
+    // dE/dcos = cos e1 (-2b) (Dpar h - Dperp (1-fin) e2) = cos e1 (-2b) ((Dpar-Dperp) h + Dperp fin);
+    // the fibre's F_k multiplies the sums once per voxel, after the loop
+    const float t = fmaf(x.dpq, h[k], x.dqfin);
+    const float dc = (cc[k] * e1[k]) * t * dSz;
     acc.r[Acc<K, LD>::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[Acc<K, LD>::kGd + 3 * k + 0]);
     acc.r[Acc<K, LD>::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[Acc<K, LD>::kGd + 3 * k + 1]);
     acc.r[Acc<K, LD>::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[Acc<K, LD>::kGd + 3 * k + 2]);
     if (LD) {
-      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 e1 (1-fin) e2, with -b = P2/2
+      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 e1 (1-fin) e2, with -b = (-2b)/2
+      const float dE = dS * x.F[2 + k];
       const float mb = 0.5f * c.z;
       const float c2 = cc[k] * cc[k];
       acc.r[Acc<K, LD>::kDpar] = fmaf(dE * E[k], mb * c2, acc.r[Acc<K, LD>::kDpar]);
@@ -304,6 +309,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
       acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe, mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
     }
   }
+  acc.r[Acc<K, LD>::kFin] = fmaf(dS, gfin, acc.r[Acc<K, LD>::kFin]);
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -575,17 +581,20 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
         }
         float gF[C], gf[C];
         float gS0 = 0.0f;
+        const float sB = sdata * D.B;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          gF[c] = sdata * acc[j].r[c];
+          gF[c] = sB * acc[j].r[c];
           gf[c] = D.S0 * gF[c];
           gS0 = fmaf(D.f[c], gF[c], gS0);
         }
         float gd[K][3];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+          const float sF = sdata * x[j].F[2 + k];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) gd[k][a] = sdata * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
+          for (int a = 0; a < 3; ++a) gd[k][a] = sF * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
+        }
         if (has_sp) {
           // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weights interleaved [V][cs]
           constexpr int C4 = (C + 3) / 4;
@@ -785,7 +794,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           const float* cal = A.th_cal + g.cal_off;
           const int32_t pc = A.coords[g.vox_off + v];
           const float lb0 = log_bias(g, cal, pc);
-          const float B0 = x[j].B;
+          const float B0 = D.B;
           float lt = 0.0f, gt = 0.0f;
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -941,7 +950,7 @@ __global__ __launch_bounds__(kBlock) void k_synth(PassArgs A) {
         const float E = ex2(kp * c2) * (x.fin + x.omf * ex2(fmaf(-kq, c2, kq)));
         S = fmaf(x.F[2 + k], E, S);
       }
-      out[(int64_t)n * V + v] = fmaf(c.x * x.B, S, c.y);
+      out[(int64_t)n * V + v] = fmaf(c.x, S, c.y);
     }
   }
   if (zero_dir && A.status) atomicOr(A.status, (uint32_t)kStZeroDir);
