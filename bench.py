@@ -42,11 +42,11 @@ METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autogr
 #     f_intra mix 1, product 1, accumulate 1 (9K); gain and offset 2 -> 9K + 5
 #   data term: residual 1, squared-residual accumulate 1                  -> 2
 #   adjoint: seed*q 1 and its accumulate 1, dS 1, dS(-2b) 1, isotropic 3,
-#     f_intra accumulate 1; per fibre fraction 1, e1 e2 1, e1(1-e2) 1,
+#     f_intra accumulate 1; per fibre fraction 1, e1(1-e2) 1 (one FMA),
 #     f_intra sum 1, bracket 1, cos e1 1, *bracket 1, *dS(-2b) 1,
-#     direction 3 (11K)                                               -> 11K + 8
-#   total 20K + 15 = 75 VALU and 2K = 6 exps.
-ALG_VALU_PER_PAIR = 75
+#     direction 3 (10K)                                               -> 10K + 8
+#   total 19K + 15 = 72 VALU and 2K = 6 exps.
+ALG_VALU_PER_PAIR = 72
 ALG_EXP_PER_PAIR = 6
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam
