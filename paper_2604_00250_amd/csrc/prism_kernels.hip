@@ -52,7 +52,7 @@ enum { kStNonfiniteLoss = 1, kStNonfiniteGrad = 2, kStZeroDir = 4 };
 // staging of one measurement: 3 x float4
 //   a = (gx, gy, gz, kpar)   kpar  = -b Dpar log2(e)   (Dpar = 1 with learned D)
 //   b = (kperp, Ecsf, Egm, Eres)                          Eq. 4
-//   c = (exp(alpha_n), beta_n, P2, Q2)  P2 = -2 b Dpar, Q2 = 2 b Dperp
+//   c = (exp(alpha_n), beta_n, -2 b, 0)                   adjoint factor
 // ---------------------------------------------------------------------------
 __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* acq) {
   const float* cal = A.th_cal + g.cal_off;
