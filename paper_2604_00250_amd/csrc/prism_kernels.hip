@@ -42,6 +42,16 @@ constexpr int kPf = PRISM_PREFETCH;
 static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
 
 enum { kMSE = 0, kNLL = 1 };
+
+// Waves per SIMD that the register allocation of the fused pass must allow:
+// three for the variants that fit 168 registers without spilling (one voxel
+// per lane, at most two fibres, or three with fixed diffusivities), else
+// PRISM_PASS_MIN_WAVES.  Those variants also let the scheduler interleave two
+// measurements at a time (sched_span 2), which the limit keeps within 168.
+constexpr int pass_min_waves(int K, bool LD, int VL) {
+  return VL == 1 && (K <= 2 || (K == 3 && !LD)) ? 3 : PRISM_PASS_MIN_WAVES;
+}
+constexpr int sched_span(int K, bool LD, int VL) { return pass_min_waves(K, LD, VL) == 3 ? 2 : 1; }
 enum {
   kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8,
   kPriorOrphan = 16, kPriorCont = 32, kPriorOrder = 64, kPriorTV = 128
@@ -382,7 +392,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
       body(t0 + u, yr[u]);
-      __builtin_amdgcn_sched_barrier(0);
+      if ((u + 1) % sched_span(K, LD, VL) == 0) __builtin_amdgcn_sched_barrier(0);
     }
   };
   // wave totals of the tile's per-measurement sums: lane l of the accumulator
@@ -865,7 +875,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
 // One block per item of one kernel variant.
 template <int K, int MODE, bool LD, int VL>
-__global__ __launch_bounds__(kBlock, PRISM_PASS_MIN_WAVES) void k_pass(
+__global__ __launch_bounds__(kBlock, pass_min_waves(K, LD, VL)) void k_pass(
     PassArgs A, const float4* __restrict__ acq_global) {
   extern __shared__ float4 smem4[];
   __shared__ PassShared sh;
