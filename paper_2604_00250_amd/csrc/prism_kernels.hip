@@ -1213,8 +1213,18 @@ __global__ __launch_bounds__(256) void k_reduce1(ReduceArgs R) {
   const int f = threadIdx.x & 63, s = threadIdx.x >> 6;
   double acc = 0.0;
   if (f < t.nf) {
+    // records r0 + s, r0 + s + 4, ...; eight loads in flight per step
     const double* base = R.rec + g.rec_off + t.f0 + f;
-    for (int r = t.r0 + s; r < t.r0 + t.nr; r += 4) acc += base[(int64_t)r * g.rec_stride];
+    const int64_t st = g.rec_stride;
+    const int r1 = t.r0 + t.nr;
+    int r = t.r0 + s;
+    for (; r + 28 < r1; r += 32) {
+      double a[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = base[(int64_t)(r + 4 * i) * st];
+      acc += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    for (; r < r1; r += 4) acc += base[(int64_t)r * st];
   }
   part[s][f] = acc;
   __syncthreads();
@@ -1232,7 +1242,17 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
   const int f = threadIdx.x & 63, s = threadIdx.x >> 6;
   const int nrr = g.item_count > 0 ? (g.item_count + 63) / 64 : 0;
   double acc = 0.0;
-  for (int rr = s; rr < nrr; rr += 4) acc += R.part[(int64_t)(g.tile_begin + fc * nrr + rr) * 64 + f];
+  {
+    // partial rows s, s + 4, ...; four loads in flight per step
+    const double* pb = R.part + (int64_t)(g.tile_begin + fc * nrr) * 64 + f;
+    int rr = s;
+    for (; rr + 12 < nrr; rr += 16) {
+      const double a0 = pb[(int64_t)rr * 64], a1 = pb[(int64_t)(rr + 4) * 64];
+      const double a2 = pb[(int64_t)(rr + 8) * 64], a3 = pb[(int64_t)(rr + 12) * 64];
+      acc += (a0 + a1) + (a2 + a3);
+    }
+    for (; rr < nrr; rr += 4) acc += pb[(int64_t)rr * 64];
+  }
   part[s][f] = acc;
   const float* cal = R.th_cal + g.cal_off;
   float* gc = R.g_cal + g.cal_off;
