@@ -332,7 +332,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // holds rows 4(l/16)..4(l/16)+3 of column l%16, so four adds and two lane
 // exchanges give the wave total for measurement n0 + l%16.  Invalid lanes
 // (beyond the item) carry valid = 0, which removes them from every sum.
-template <int K, int MODE, bool LD, int VL>
+// FULL: every lane's voxels are in the item (the validity factors are 1 and
+// drop out at compile time).
+template <int K, int MODE, bool LD, int VL, bool FULL>
 __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<K, LD> (&acc)[VL],
                                                  const float* yg, int64_t V, const int (&vox)[VL],
                                                  const float (&valid)[VL],
@@ -366,7 +368,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll
     for (int j = 0; j < VL; ++j) {
       float tl, ts, sq, sd;
-      pair<K, MODE, LD>(x[j], acc[j], slot[j], valid[j], a, b, c, inv_s2, tl, ts, sq, sd);
+      pair<K, MODE, LD>(x[j], acc[j], slot[j], FULL ? 1.0f : valid[j], a, b, c, inv_s2, tl, ts, sq, sd);
       lacc += tl;
       if (MODE == kNLL) sacc += ts;
       pa = j == 0 ? sq : pa + sq;
@@ -547,8 +549,13 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
       for (int i = 0; i < NACC; ++i) acc[j].r[i] = 0.0f;
     }
 
-    measurement_loop<K, MODE, LD, VL>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
-                                      wacc, dloss, dsig);
+    // a chunk that lies wholly inside the item runs the loop without validity factors
+    if (cb + chunk <= it.nv)
+      measurement_loop<K, MODE, LD, VL, true>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
+                                              wacc, dloss, dsig);
+    else
+      measurement_loop<K, MODE, LD, VL, false>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
+                                               wacc, dloss, dsig);
 
     // combine the per-voxel accumulators of the waves that split this row over n
     if (WN > 1) {
