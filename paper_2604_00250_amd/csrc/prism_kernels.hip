@@ -621,17 +621,30 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
           for (int q = 0; q < C4; ++q) sum[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
           int cnt = 0;
-          for (int q = 0; q < g.nbh; ++q) {
-            const int u = nbr[(int64_t)q * V + v];
-            if (u >= 0) {
-              ++cnt;
+          // six neighbours per round trip: their table entries, then their weight
+          // rows (an absent neighbour reads this voxel's row with factor 0)
+          constexpr int kNb = 6;
+          for (int q0 = 0; q0 < g.nbh; q0 += kNb) {
+            int u[kNb];
+#pragma unroll
+            for (int e = 0; e < kNb; ++e) u[e] = q0 + e < g.nbh ? nbr[(int64_t)(q0 + e) * V + v] : -1;
+            float4 t[kNb][C4];
+#pragma unroll
+            for (int e = 0; e < kNb; ++e) {
+              const int64_t src = (int64_t)(u[e] >= 0 ? u[e] : v) * C4;
+#pragma unroll
+              for (int i = 0; i < C4; ++i) t[e][i] = w4[src + i];
+            }
+#pragma unroll
+            for (int e = 0; e < kNb; ++e) {
+              const float on = u[e] >= 0 ? 1.0f : 0.0f;
+              cnt += u[e] >= 0 ? 1 : 0;
 #pragma unroll
               for (int i = 0; i < C4; ++i) {
-                const float4 t = w4[(int64_t)u * C4 + i];
-                sum[i].x += t.x;
-                sum[i].y += t.y;
-                sum[i].z += t.z;
-                sum[i].w += t.w;
+                sum[i].x = fmaf(on, t[e][i].x, sum[i].x);
+                sum[i].y = fmaf(on, t[e][i].y, sum[i].y);
+                sum[i].z = fmaf(on, t[e][i].z, sum[i].z);
+                sum[i].w = fmaf(on, t[e][i].w, sum[i].w);
               }
             }
           }
