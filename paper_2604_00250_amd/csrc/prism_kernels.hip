@@ -781,9 +781,9 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           float* th = A.th_upd + g.micro_off;
           float* mm = A.m_micro + g.micro_off;
           float* vv = A.v_micro + g.micro_off;
-          // in batches of kAdamBatch parameters: the batch's loads are issued
+          // in two batches of parameters: each batch's loads are issued
           // together so that their latencies overlap, in few registers
-          constexpr int kAdamBatch = 8;
+          constexpr int kAdamBatch = (P + 1) / 2;
 #pragma unroll
           for (int p0 = 0; p0 < P; p0 += kAdamBatch) {
             float pp[kAdamBatch], m1[kAdamBatch], v1[kAdamBatch];
