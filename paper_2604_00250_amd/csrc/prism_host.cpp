@@ -424,6 +424,13 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
     g.nx = d.nx;
     g.ny = d.ny;
     g.nz = d.nz;
+    {
+      const int32_t n3[3] = {d.nx, d.ny, d.nz};
+      for (int a = 0; a < 3; ++a) {
+        g.bsc[a] = n3[a] > 1 ? 2.0f / (float)(n3[a] - 1) : 0.0f;
+        g.boff[a] = n3[a] > 1 ? -1.0f : 0.0f;
+      }
+    }
     g.acq_off = acq_off[d.acq];
     g.rec_stride = kRecHead + 2 * g.N;
     g.invM = V > 0 ? 1.0f / (float)V : 0.0f;

@@ -49,6 +49,8 @@ struct GroupDev {
   int32_t ntab;       // neighbour-table entries (nbh, or 6 for the bias TV alone)
   int32_t cs;         // per-voxel stride of the interleaved fractions / weights (C rounded up to 4)
   int32_t nx, ny, nz;
+  float bsc[3], boff[3]; // quadratic bias coordinates xi_a = i_a bsc[a] + boff[a] in [-1, 1]
+                         // (2/(n_a - 1) and -1; both 0 when n_a = 1)
   int32_t acq_off;    // offset of the group's measurements in the acquisition arrays
   int32_t rec_stride; // float64 fields per record
   int32_t item_begin, item_count;

@@ -130,9 +130,10 @@ __device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, i
   if (g.bias == 0) return 0.0f;
   const int i = pc & 1023, j = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
   if (g.bias == 1) {
-    const float x = g.nx > 1 ? (2.0f * i - (g.nx - 1)) / (float)(g.nx - 1) : 0.0f;
-    const float y = g.ny > 1 ? (2.0f * j - (g.ny - 1)) / (float)(g.ny - 1) : 0.0f;
-    const float z = g.nz > 1 ? (2.0f * k - (g.nz - 1)) / (float)(g.nz - 1) : 0.0f;
+    // xi_a = (2 i_a - (n_a - 1)) / (n_a - 1) as one FMA with per-group constants
+    const float x = fmaf((float)i, g.bsc[0], g.boff[0]);
+    const float y = fmaf((float)j, g.bsc[1], g.boff[1]);
+    const float z = fmaf((float)k, g.bsc[2], g.boff[2]);
     float s = cal[0];
     s = fmaf(cal[1], x, s);
     s = fmaf(cal[2], y, s);
@@ -845,9 +846,10 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
         if (g.bias == 1) {
           const int32_t pc = A.coords[g.vox_off + v];
           const int i = pc & 1023, jj = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
-          const float xx = g.nx > 1 ? (2.0f * i - (g.nx - 1)) / (float)(g.nx - 1) : 0.0f;
-          const float yy = g.ny > 1 ? (2.0f * jj - (g.ny - 1)) / (float)(g.ny - 1) : 0.0f;
-          const float zz = g.nz > 1 ? (2.0f * k - (g.nz - 1)) / (float)(g.nz - 1) : 0.0f;
+          // the coordinates of log_bias, bit for bit
+          const float xx = fmaf((float)i, g.bsc[0], g.boff[0]);
+          const float yy = fmaf((float)jj, g.bsc[1], g.boff[1]);
+          const float zz = fmaf((float)k, g.bsc[2], g.boff[2]);
           const float phi[10] = {1.0f, xx, yy, zz, xx * xx, yy * yy, zz * zz, xx * yy, xx * zz, yy * zz};
 #pragma unroll
           for (int q = 0; q < 10; ++q) ep_b[q][tid] = fmaf(phi[q], glb, ep_b[q][tid]);
