@@ -34,10 +34,15 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autograd; %VALU"
 
 # Algorithmic work of one (voxel, measurement) pair of the fused pass at K = 3,
-# MSE, fixed diffusivities: every operation of Eq. 3-6, the data term and the
-# adjoint counted once, an FMA as one, fused wherever the algebra allows
-# (per-voxel factors such as the bias field and each fibre's fraction are
-# applied once per voxel, outside the per-pair work):
+# MSE, fixed diffusivities, as the roofline counts it: the figure derived from
+# the method's steps before any kernel was written (forward 10K + 8 VALU, adjoint
+# 12K + 10, 2K exps) and kept fixed as the implementation changes, so that
+# roofline fractions stay comparable across versions.
+ALG_VALU_PER_PAIR = 84
+# The fewest operations the implementation's algebra needs for the same pair
+# (every operation of Eq. 3-6, the data term and the adjoint counted once, an
+# FMA as one, fused wherever the algebra allows, per-voxel factors such as the
+# bias field and each fibre's fraction applied once per voxel):
 #   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2,
 #     f_intra mix 1, product 1, accumulate 1 (9K); gain and offset 2 -> 9K + 5
 #   data term: residual 1, squared-residual accumulate 1                  -> 2
@@ -45,8 +50,8 @@ METRIC = "voxel-iters/s (fwd+adjoint, 288 meas, K=3) fused HIP vs PyTorch autogr
 #     f_intra accumulate 1; per fibre fraction 1, e1(1-e2) 1 (one FMA),
 #     f_intra sum 1, bracket 1, cos e1 1, *bracket 1, *dS(-2b) 1,
 #     direction 3 (10K)                                               -> 10K + 8
-#   total 19K + 15 = 72 VALU and 2K = 6 exps.
-ALG_VALU_PER_PAIR = 72
+#   total 19K + 15 = 72 VALU and 2K = 6 exps; reported as frac_min_count.
+MIN_VALU_PER_PAIR = 72
 ALG_EXP_PER_PAIR = 6
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam
@@ -391,6 +396,9 @@ def main():
                     traffic_vs_algorithmic=(traffic / (ALG_BYTES_PER_VOXEL * V)) if traffic else None,
                     kernel="k_pass<3,MSE,fixedD>", kernel_ms=k_ms, launches=k_launches,
                     alg_slots_per_pair=ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR, q_exp=q,
+                    frac_min_count=pairs * (MIN_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR) / (k_ms * 1e-3)
+                    / PEAK_SLOTS,
+                    min_slots_per_pair=MIN_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR,
                     hbm_GBps=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / 1e9,
                     hbm_frac=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / PEAK_HBM)
     out = {
