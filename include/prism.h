@@ -169,7 +169,9 @@ typedef struct {
   int32_t n_split;      /* 1, 2 or 4 waves sharing one voxel row (each over a part of
                            the measurements); 0 = chosen per work item from its size */
   int32_t item_vox;     /* voxels per work item (one thread block at a time), a
-                           multiple of 64 * vox_per_lane * 4 / n_split; 0 = automatic */
+                           multiple of 64 * vox_per_lane * 4 / n_split; 0 = automatic:
+                           one block chunk (that multiple) with a fixed n_split, else
+                           about six blocks per compute unit over the problem */
   int32_t persistent;   /* 0: one launch per kernel variant (K, mode, learned D);
                            1: one persistent launch over all work items, largest
                            first, each block popping items from a device counter */
