@@ -262,7 +262,7 @@ def bench_batched(args):
     from paper_2604_00250_amd.problem import DeviceState, Problem
     from paper_2604_00250_amd.tune import autotune
     t0 = time.time()
-    w = I.config3()
+    w = I.batched_patches()
     log(f"workload {w.name}: {len(w.groups)} patches, {w.n_vox} voxels, generated in {time.time() - t0:.1f} s")
     prob = Problem(w.groups)
     st = DeviceState(prob, ys=[g.y for g in w.groups], thetas=[g.theta for g in w.groups], device="cuda:0")
@@ -318,8 +318,8 @@ def main():
                          "independent uneven patches in one problem, autotuned launch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures the single-GPU path only: this build runs the fused pass on one "
-              "MI355X (multi-GPU sharding is described in DESIGN.md, not run). Use --gpus 1.",
+        print("bench.py measures the single-GPU path only: the fused pass runs on one MI355X "
+              "and sharding over several GPUs is not implemented. Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -329,7 +329,7 @@ def main():
     if args.workload == "batched":
         return bench_batched(args)
     t0 = time.time()
-    w = I.config2()
+    w = I.brain_volume()
     g = w.groups[0]
     log(f"workload {w.name}: {g.n_vox} voxels, N={g.acq.n}, K={g.K}, generated in {time.time() - t0:.1f} s")
     # the CPU leg runs first, in worker processes forked before this process touches the GPU

@@ -71,7 +71,7 @@ extern "C" {
 typedef enum {
   PRISM_OK = 0,
   PRISM_E_INVALID = -1,     /* bad argument: null pointer, size or enum out of range */
-  PRISM_E_UNSUPPORTED = -2, /* well-formed but not provided by this build */
+  PRISM_E_UNSUPPORTED = -2, /* well-formed but not supported by the library */
   PRISM_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
   PRISM_E_WORKSPACE = -4,   /* workspace smaller than prism_workspace_bytes() */
   PRISM_E_ALLOC = -5        /* host or device allocation failed (create/tune only) */

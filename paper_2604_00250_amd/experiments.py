@@ -150,7 +150,7 @@ def run_optimizers(iterations=200, shape=(81, 106, 20), target=60_000, seed=None
     from . import inputs as I
     from .fit import fit
     from .problem import DeviceState, Problem
-    w = I.config2(seed=seed, shape=shape, target=target, acq_kind="hardi160")
+    w = I.brain_volume(seed=seed, shape=shape, target=target, acq_kind="hardi160")
     g = w.groups[0]
     prob = Problem([g])
     curves = {}

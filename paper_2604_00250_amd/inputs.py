@@ -22,8 +22,10 @@ Layout conventions shared by every consumer:
   * calibration parameters: bias [n_bias], alpha [N], beta [N], sigma_log ();
   * measurements y are ``[N, V]`` float32.
 
-Seeds: config i uses ``SeedSequence(1000 + i)`` spawned into independent
-streams (acquisition, tissue, directions, noise, calibration, init).
+Seeds: the i-th generator below (0 patch8_crossings, 1 patch16_hcp,
+2 brain_volume, 3 batched_patches, 4 tube_phantom) uses ``SeedSequence(1000 + i)``
+spawned into independent streams (acquisition, tissue, directions, noise,
+calibration, init).
 """
 from __future__ import annotations
 
@@ -393,7 +395,7 @@ def _single_patch(index, edge, acq_kind, K, mode, snr, bias, sigma_init_factor,
     return Workload(name=name, groups=[g], iterations=iterations)
 
 
-def config0(seed=None, priors=("rep",)) -> Workload:
+def patch8_crossings(seed=None, priors=("rep",)) -> Workload:
     """8^3 patch, K=3, 33 single-shell measurements, MSE, SNR 30, 100 Adam steps."""
     w = _single_patch(0, 8, "single33", 3, "mse", 30.0, "none", 0.0, 100, False, seed,
                       name="patch8_n33_k3_mse")
@@ -402,7 +404,7 @@ def config0(seed=None, priors=("rep",)) -> Workload:
     return w
 
 
-def config1(seed=None) -> Workload:
+def patch16_hcp(seed=None) -> Workload:
     """16^3 patch, K=3, 288 three-shell measurements, Rician NLL with learned
     sigma (initialised at twice the truth), quadratic bias + gains, 500 iterations."""
     w = _single_patch(1, 16, "three288", 3, "nll", 30.0, "poly2", 2.0, 500, True, seed,
@@ -469,7 +471,7 @@ def _separate(dirs, min_angle=20.0):
     return dirs
 
 
-def config2(seed=None, shape=(145, 174, 145), target=741_000, with_y=True, acq_kind="three288") -> Workload:
+def brain_volume(seed=None, shape=(145, 174, 145), target=741_000, with_y=True, acq_kind="three288") -> Workload:
     """Whole-brain-shaped volume: ellipsoid mask of ~741k voxels, smooth tissue
     maps (CSF shell, GM rim, WM core with 1-3 fibres following smooth direction
     fields), N=288 three-shell, K=3, MSE, calibration on at identity, SNR 30.
@@ -515,7 +517,7 @@ def config2(seed=None, shape=(145, 174, 145), target=741_000, with_y=True, acq_k
                                  "calibration (quadratic log-bias, gains, offsets) at identity, SNR 30"))
 
 
-def config3(seed=None, n_patches=4096, edge_range=(4, 24), with_y=True) -> Workload:
+def batched_patches(seed=None, n_patches=4096, edge_range=(4, 24), with_y=True) -> Workload:
     """Many independent patches of uneven size: edge round(exp U(ln4, ln24)),
     acquisition in {33, 96, 288}, K in 1..5, MSE or NLL (p = 1/2), SNR U(10, 50)."""
     r_acq, r_tis, r_dir, r_noise, r_cal, r_init = streams(3, seed)
@@ -544,7 +546,7 @@ def config3(seed=None, n_patches=4096, edge_range=(4, 24), with_y=True) -> Workl
                                  "MSE or NLL, SNR U(10,50)"))
 
 
-def config4(seed=None, edge=40, n_tubes=8) -> Workload:
+def tube_phantom(seed=None, edge=40, n_tubes=8) -> Workload:
     """40^3 volume with 8 straight tubular bundles (radius U(3,6)) crossing at
     20-90 degrees, N=96 two-shell, K=4, Rician NLL with learned sigma and
     learned diffusivities, SNR 20."""
@@ -687,8 +689,10 @@ def crossing_benchmark(snr: float = 30.0, seed=None, per_angle: int = 200, n_sin
     return Workload(name=name, groups=[g], iterations=300, description=name)
 
 
-CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
+WORKLOADS = {"patch8_crossings": patch8_crossings, "patch16_hcp": patch16_hcp,
+             "brain_volume": brain_volume, "batched_patches": batched_patches,
+             "tube_phantom": tube_phantom}
 
 
-def make_config(i: int, seed=None, **kw) -> Workload:
-    return CONFIGS[i](seed=seed, **kw)
+def make_workload(name: str, seed=None, **kw) -> Workload:
+    return WORKLOADS[name](seed=seed, **kw)

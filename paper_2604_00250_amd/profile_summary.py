@@ -35,7 +35,7 @@ def stats_summary(stats_csv, bench_json, out_md, command):
 
 
 def kernel_source_hash(root=None) -> str:
-    """SHA-1 of the kernel sources (a profile's counters describe this build only)."""
+    """SHA-1 of the kernel sources (a profile's counters hold only for kernels built from them)."""
     import hashlib
     import os
     here = root or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")

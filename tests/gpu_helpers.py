@@ -144,7 +144,7 @@ _FULL = {}
 def _full_workload(perturb_seed):
     key = ("cfg2", perturb_seed)
     if key not in _FULL:
-        w = I.config2()
+        w = I.brain_volume()
         g = w.groups[0]
         if perturb_seed is not None:
             g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(perturb_seed), scale=0.5))

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _workload(n=96, edges=(2, 12)):
-    w = I.config3(n_patches=n, edge_range=edges)
+    w = I.batched_patches(n_patches=n, edge_range=edges)
     for g in w.groups:  # a generic parameter point, not the symmetric init
         g.theta = I.perturb_theta(g.theta, np.random.default_rng(g.n_vox), scale=0.5)
     return w

@@ -24,7 +24,7 @@ def test_autograd_function_matches_oracle_and_fp64_finite_differences():
     against central differences (h = 1e-6) of the FP64 oracle objective."""
     import torch
     from paper_2604_00250_amd.autograd import PrismLoss
-    w = I.config4()
+    w = I.tube_phantom()
     g = I.sub_box(w.groups[0], I.crossing_subpatch(w, 4), 4)
     g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(17)))
     st = _state([g])
@@ -135,7 +135,7 @@ def test_short_adam_trajectory_matches_oracle():
     follow the FP64 oracle's trajectory (Adam on the oracle gradient)."""
     import torch
     from paper_2604_00250_amd.fit import fit
-    g = I.config0(priors=I.PRIOR_NAMES).groups[0]
+    g = I.patch8_crossings(priors=I.PRIOR_NAMES).groups[0]
     st = _state([g])
     hist = fit(st, 5, lr=1e-2, graph=True)
     torch.cuda.synchronize()
@@ -164,7 +164,7 @@ def test_short_adam_trajectory_matches_oracle():
 def test_fit_reduces_loss_on_the_calibrated_patch():
     import torch
     from paper_2604_00250_amd.fit import fit
-    g = I.config1().groups[0]
+    g = I.patch16_hcp().groups[0]
     st = _state([g])
     hist = fit(st, 60, lr=1e-2, graph=True)
     torch.cuda.synchronize()

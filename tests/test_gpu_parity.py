@@ -32,7 +32,7 @@ def _check_groups(name, groups, launch=None, loss_rtol=1e-5, grad_rtol=1e-4):
 @pytest.mark.parametrize("priors", [("rep",), I.PRIOR_NAMES])
 @pytest.mark.parametrize("perturb", [False, True])
 def test_patch8_n33_mse(priors, perturb):
-    w = I.config0(priors=priors)
+    w = I.patch8_crossings(priors=priors)
     g = w.groups[0]
     if perturb:
         g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(5)))
@@ -41,14 +41,14 @@ def test_patch8_n33_mse(priors, perturb):
 
 @pytest.mark.parametrize("perturb", [False, True])
 def test_patch16_n288_nll_calibrated(perturb):
-    g = I.config1().groups[0]
+    g = I.patch16_hcp().groups[0]
     if perturb:
         g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(6)))
     _check_groups(f"patch16 nll perturb={perturb}", [g])
 
 
 def test_phantom_crossing_subpatch_learned_diffusivities():
-    w = I.config4()
+    w = I.tube_phantom()
     corner = I.crossing_subpatch(w, 4)
     g = I.sub_box(w.groups[0], corner, 4)
     g = with_theta(g, I.perturb_theta(g.theta, np.random.default_rng(7)))

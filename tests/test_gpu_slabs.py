@@ -76,7 +76,7 @@ def test_stitch_kernel_matches_oracle_on_independent_slab_parameters():
     fibre matching."""
     from paper_2604_00250_amd.problem import DeviceState
     from paper_2604_00250_amd.slabs import SlabFit
-    g = I.config4().groups[0]
+    g = I.tube_phantom().groups[0]
     fit = SlabFit(g, thickness=30, overlap=5)
     rng = np.random.default_rng(71)
     ths = [I.perturb_theta(s.theta, rng, scale=1.0) for s in fit.slabs]
@@ -91,7 +91,7 @@ def test_slab_fit_on_a_brain_shaped_volume_then_stitch():
     fitted on the GPU in one batched problem; every slab's loss falls, and
     the stitched maps of the fitted parameters match the oracle's stitch."""
     from paper_2604_00250_amd.slabs import SlabFit
-    w = I.config2(shape=(40, 48, 64), target=30_000)
+    w = I.brain_volume(shape=(40, 48, 64), target=30_000)
     g = w.groups[0]
     fit = SlabFit(g, thickness=30, overlap=5)
     assert [t for _, t in fit.ranges] == [30, 30, 14]

@@ -17,7 +17,7 @@ def test_slab_ranges_agree_with_the_oracle(nz, T, ov):
 
 
 def test_split_partitions_voxels_and_keeps_calibration_separate():
-    g = I.config1().groups[0]
+    g = I.patch16_hcp().groups[0]
     ranges = S.slab_ranges(g.shape[2], 6, 2)
     parts = S.split_into_slabs(g, ranges)
     z = g.coords[:, 2]
