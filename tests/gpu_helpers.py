@@ -142,7 +142,7 @@ _FULL = {}
 
 
 def _full_workload(perturb_seed):
-    key = ("cfg2", perturb_seed)
+    key = ("brain_volume", perturb_seed)
     if key not in _FULL:
         w = I.brain_volume()
         g = w.groups[0]
