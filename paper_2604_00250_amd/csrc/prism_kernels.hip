@@ -461,11 +461,22 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
 // Adam's step-dependent factors for t = step[0] + 1, in float64 as k_adam takes them
 __device__ __forceinline__ void adam_factors(const int32_t* step, float lr, float b1, float b2,
                                              float& step_size, float& ibc2) {
-  const int t = step[0] + 1;
-  const double bc1 = 1.0 - pow((double)b1, (double)t);
-  const double bc2 = 1.0 - pow((double)b2, (double)t);
-  step_size = (float)((double)lr / bc1);
-  ibc2 = (float)(1.0 / sqrt(bc2));
+  // b1^t and b2^t by repeated squaring over the bits of t (a few float64
+  // multiplies where a general pow costs hundreds of instructions, on the
+  // thread that every wave of the fused pass's block waits for)
+  unsigned t = (unsigned)step[0] + 1u;
+  double p1 = 1.0, p2 = 1.0, x1 = (double)b1, x2 = (double)b2;
+  while (t) {
+    if (t & 1u) {
+      p1 *= x1;
+      p2 *= x2;
+    }
+    x1 *= x1;
+    x2 *= x2;
+    t >>= 1;
+  }
+  step_size = (float)((double)lr / (1.0 - p1));
+  ibc2 = (float)(1.0 / sqrt(1.0 - p2));
 }
 
 // statically sized LDS of the fused pass (one instance per kernel, shared by the
