@@ -17,7 +17,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libprism.so")
-SOURCES = ["prism_kernels.hip", "prism_host.cpp"]
+# (source, object, extra flags): the fused pass is compiled once per fibre count K
+# so that its 48 template variants build in parallel
+SOURCES = ([("prism_kernels.hip", "prism_kernels.o", []), ("prism_persistent.hip", "prism_persistent.o", [])]
+           + [("prism_pass_k.hip", f"prism_pass_k{k}.o", [f"-DPRISM_PASS_K={k}"]) for k in range(1, 7)]
+           + [("prism_host.cpp", "prism_host.o", [])])
 ARCH = "gfx950"
 
 
@@ -35,10 +39,10 @@ def build(verbose: bool = False) -> str:
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(HERE, "..", "include")]
-    for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+    for src, obj_name, extra in SOURCES:
+        obj = os.path.join(CSRC, obj_name)
         objs.append(obj)
-        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + flags + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -145,6 +145,9 @@ hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
                                   hipStream_t s);
 int persistent_blocks_per_cu(int maxN, int xsplit);
+// every fused-pass variant of one K (one translation unit per K)
+template <int K>
+hipError_t launch_pass_k(const PassArgs& a, int mode, int learn_d, int vpl, int maxN, hipStream_t s);
 hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
                             hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int max_tile_fields, hipStream_t s);

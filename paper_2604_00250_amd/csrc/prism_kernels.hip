@@ -1,10 +1,7 @@
-// HIP kernels of the PRISM analysis-by-synthesis pass for gfx950 (CDNA4, wave64).
+// HIP kernels of the PRISM analysis-by-synthesis pass for gfx950 (CDNA4, wave64)
+// other than the fused pass itself (prism_pass.h, instantiated per K in
+// prism_pass_k.hip, and its persistent form in prism_persistent.hip):
 //
-// k_pass      fused forward (Eq. 3-6) + data term (Eq. 8/9) + adjoint, one
-//             thread block per work item (a contiguous run of one group's
-//             voxels); lane = voxel, loop over measurements with the
-//             acquisition staged in LDS; exps are recomputed, never stored.
-// k_synth     forward model only (yhat).
 // k_fractions, k_spatial  Eq. 7: softmax fractions, then the residual weights
 //             rho'(r)/|N| per voxel and compartment.
 // k_reduce1/2 deterministic two-stage reduction of per-item records into the
@@ -12,1016 +9,11 @@
 // k_bias_tri  gradient of the 8^3 trilinear log-bias grid.
 // k_stitch    blend of per-slab maps into whole-volume maps (slab fitting).
 // k_adam, k_rprop  optimiser steps.
-#include "prism_device.h"
-#include "prism_internal.h"
+#include <algorithm>
+
+#include "prism_common.h"
 
 namespace prism {
-
-#ifndef PRISM_PASS_MIN_WAVES
-#define PRISM_PASS_MIN_WAVES 1
-#endif
-#ifndef PRISM_STEP_BARRIER
-#define PRISM_STEP_BARRIER 0
-#endif
-#ifndef PRISM_TILE
-#define PRISM_TILE 16
-#endif
-#ifndef PRISM_PERSISTENT_MIN_WAVES
-#define PRISM_PERSISTENT_MIN_WAVES 2
-#endif
-#ifndef PRISM_ACQ_SMEM
-#define PRISM_ACQ_SMEM 0
-#endif
-#ifndef PRISM_PREFETCH
-#define PRISM_PREFETCH 4
-#endif
-// measurements per matrix-core reduction tile (8 or 16 columns of the 16x16 tile)
-constexpr int kTile = PRISM_TILE;
-// depth of the y prefetch ring (measurements ahead); kTile is a multiple of it
-constexpr int kPf = PRISM_PREFETCH;
-static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
-
-enum { kMSE = 0, kNLL = 1 };
-
-// Waves per SIMD that the register allocation of the fused pass must allow:
-// three for the variants that fit 168 registers without spilling (one voxel
-// per lane, at most two fibres, or three with fixed diffusivities), else
-// PRISM_PASS_MIN_WAVES.  Those variants also let the scheduler interleave two
-// measurements at a time (sched_span 2), which the limit keeps within 168.
-constexpr int pass_min_waves(int K, bool LD, int VL) {
-  return VL == 1 && (K <= 2 || (K == 3 && !LD)) ? 3 : PRISM_PASS_MIN_WAVES;
-}
-constexpr int sched_span(int K, bool LD, int VL) { return pass_min_waves(K, LD, VL) == 3 ? 2 : 1; }
-enum {
-  kPriorSpatial = 1, kPriorRep = 2, kPriorSparse = 4, kPriorCal = 8,
-  kPriorOrphan = 16, kPriorCont = 32, kPriorOrder = 64, kPriorTV = 128
-};
-enum { kStNonfiniteLoss = 1, kStNonfiniteGrad = 2, kStZeroDir = 4 };
-
-// ---------------------------------------------------------------------------
-// staging of one measurement: 3 x float4
-//   a = (gx, gy, gz, kpar)   kpar  = -b Dpar log2(e)   (Dpar = 1 with learned D)
-//   b = (kperp, Ecsf, Egm, Eres)                          Eq. 4
-//   c = (exp(alpha_n), beta_n, -2 b, 0)                   adjoint factor
-// ---------------------------------------------------------------------------
-__device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* acq) {
-  const float* cal = A.th_cal + g.cal_off;
-  const float* alpha = cal + g.n_bias;
-  const float* beta = alpha + g.N;
-  const float dpar = g.learn_d ? 1.0f : A.model.d_par;
-  const float dperp = g.learn_d ? 1.0f : A.model.d_perp;
-  for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
-    const float b = A.bval[g.acq_off + n];
-    const float* gv = A.bvec + 3 * (int64_t)(g.acq_off + n);
-    acq[3 * n + 0] = make_float4(gv[0], gv[1], gv[2], -b * dpar * kLog2e);
-    acq[3 * n + 1] = make_float4(-b * dperp * kLog2e, expf(-b * A.model.d_csf),
-                                 expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
-    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b, 0.0f);
-  }
-}
-
-// The same table written once per call to the workspace, read by the fused
-// pass through the scalar cache (uniform loads into SGPRs).
-__global__ __launch_bounds__(256) void k_stage(PassArgs A) {
-  const GroupDev g = A.groups[blockIdx.x];
-  stage_acquisition(A, g, reinterpret_cast<float4*>(A.wsp + g.acqtab_off));
-}
-
-// ---------------------------------------------------------------------------
-// per-voxel state
-// ---------------------------------------------------------------------------
-template <int K, bool LD>
-struct Vox {
-  float F[K + 3];   // B S0 * fraction (bias field folded in), order csf, gm, wm_0..wm_{K-1}, res
-  float d[K][3];    // unit directions
-  float fin, omf;   // f_intra, 1 - f_intra
-  float dpq, dqfin; // Dpar - Dperp, Dperp f_intra (the fibre-angle adjoint)
-  float dpar, dperp;
-};
-
-// per-voxel adjoint accumulators as one register array (constant indices only)
-template <int K, bool LD>
-struct Acc {
-  static constexpr int C = K + 3;
-  static constexpr int kGd = C;               // sum_n dc_k g_n / F_k (dL/dd_k / F_k), 3K
-  static constexpr int kFin = C + 3 * K;      // sum_n sum_k dE_k e1 (1 - e2)
-  static constexpr int kLogB = C + 3 * K + 1; // sum_n seed (yhat - beta)
-  static constexpr int kDpar = C + 3 * K + 2; // learned diffusivities
-  static constexpr int kDperp = C + 3 * K + 3;
-  static constexpr int N = C + 3 * K + 2 + (LD ? 2 : 0);
-  float r[N];                                 // r[c] = sum_n dS E_c (dL/dF_c / B)
-};
-
-// raw parameter rows of theta_micro [P][V]
-__device__ __forceinline__ int row_logit(int c) { return 1 + c; }
-__device__ __forceinline__ int row_v(int C, int k, int a) { return C + 1 + 3 * k + a; }
-__device__ __forceinline__ int row_fin(int C, int K) { return C + 1 + 3 * K; }
-__device__ __forceinline__ int row_dpar(int C, int K) { return C + 2 + 3 * K; }
-
-struct Derived {            // quantities the epilogue needs again
-  float S0, sig_s;
-  float f[kMaxC];
-  float invn[kMaxK];
-  float sig_dpar, sig_dperp;
-  float B;                  // bias field
-};
-
-__device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, int32_t pc) {
-  if (g.bias == 0) return 0.0f;
-  const int i = pc & 1023, j = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
-  if (g.bias == 1) {
-    // xi_a = (2 i_a - (n_a - 1)) / (n_a - 1) as one FMA with per-group constants
-    const float x = fmaf((float)i, g.bsc[0], g.boff[0]);
-    const float y = fmaf((float)j, g.bsc[1], g.boff[1]);
-    const float z = fmaf((float)k, g.bsc[2], g.boff[2]);
-    float s = cal[0];
-    s = fmaf(cal[1], x, s);
-    s = fmaf(cal[2], y, s);
-    s = fmaf(cal[3], z, s);
-    s = fmaf(cal[4], x * x, s);
-    s = fmaf(cal[5], y * y, s);
-    s = fmaf(cal[6], z * z, s);
-    s = fmaf(cal[7], x * y, s);
-    s = fmaf(cal[8], x * z, s);
-    s = fmaf(cal[9], y * z, s);
-    return s;
-  }
-  // trilinear 8^3: control point c sits at voxel c (n-1)/7 along each axis
-  float p[3];
-  int i0[3];
-  const int ii[3] = {i, j, k};
-  const int nn[3] = {g.nx, g.ny, g.nz};
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float pa = nn[a] > 1 ? ii[a] * (7.0f / (float)(nn[a] - 1)) : 0.0f;
-    int c = (int)floorf(pa);
-    c = c > 6 ? 6 : c;
-    i0[a] = c;
-    p[a] = pa - c;
-  }
-  float s = 0.0f;
-#pragma unroll
-  for (int cx = 0; cx < 2; ++cx)
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int cz = 0; cz < 2; ++cz) {
-        const float w = (cx ? p[0] : 1.0f - p[0]) * (cy ? p[1] : 1.0f - p[1]) *
-                        (cz ? p[2] : 1.0f - p[2]);
-        s = fmaf(w, cal[((i0[0] + cx) * 8 + (i0[1] + cy)) * 8 + (i0[2] + cz)], s);
-      }
-  return s;
-}
-
-// Raw parameters of voxel v -> constrained quantities (Sec. 2.2, 2.5).  Called
-// in the prologue (Vox for the measurement loop) and again in the epilogue
-// (Derived for the chain rule), so that nothing but Vox stays live across the
-// measurement loop.
-template <int K, bool LD>
-__device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g, int v,
-                                           Vox<K, LD>& x, Derived& dv, bool& zero_dir) {
-  constexpr int C = K + 3;
-  const float* th = A.th_micro + g.micro_off;
-  const int64_t V = g.V;
-  const float s = th[v];
-  dv.S0 = softplus_f(s);
-  dv.sig_s = sigmoid_f(s);
-  float lg[C];
-  float m = -INFINITY;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    lg[c] = th[(int64_t)row_logit(c) * V + v];
-    m = fmaxf(m, lg[c]);
-  }
-  float sum = 0.0f;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    lg[c] = exp_hw(lg[c] - m);
-    sum += lg[c];
-  }
-  const float inv = rcp(sum);
-  const float* cal = A.th_cal + g.cal_off;
-  dv.B = exp_hw(log_bias(g, cal, A.coords[g.vox_off + v]));
-  const float BS0 = dv.B * dv.S0;
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    dv.f[c] = lg[c] * inv;
-    x.F[c] = BS0 * dv.f[c];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float vx = th[(int64_t)row_v(C, k, 0) * V + v];
-    const float vy = th[(int64_t)row_v(C, k, 1) * V + v];
-    const float vz = th[(int64_t)row_v(C, k, 2) * V + v];
-    const float n2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
-    float in = 0.0f;
-    if (n2 > 0.0f) {
-      in = rsq(n2);
-    } else {
-      zero_dir = true;
-    }
-    dv.invn[k] = in;
-    x.d[k][0] = vx * in;
-    x.d[k][1] = vy * in;
-    x.d[k][2] = vz * in;
-  }
-  x.fin = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
-  x.omf = 1.0f - x.fin;
-  if (LD) {
-    const float a = th[(int64_t)row_dpar(C, K) * V + v];
-    const float b = th[(int64_t)(row_dpar(C, K) + 1) * V + v];
-    x.dpar = softplus_f(a);
-    x.dperp = softplus_f(b);
-    dv.sig_dpar = sigmoid_f(a);
-    dv.sig_dperp = sigmoid_f(b);
-  } else {
-    x.dpar = 0.0f;
-    x.dperp = 0.0f;
-    dv.sig_dpar = 0.0f;
-    dv.sig_dperp = 0.0f;
-  }
-  const float dperp = LD ? x.dperp : A.model.d_perp;
-  x.dpq = (LD ? x.dpar : A.model.d_par) - dperp;
-  x.dqfin = dperp * x.fin;
-}
-
-// ---------------------------------------------------------------------------
-// one (voxel, measurement) pair: forward, data term, adjoint accumulation
-// ---------------------------------------------------------------------------
-template <int K, int MODE, bool LD>
-__device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv, float valid,
-                                     const float4 a, const float4 b, const float4 c, float inv_s2,
-                                     float& t_loss, float& t_sig, float& sq, float& seed) {
-  const float gx = a.x, gy = a.y, gz = a.z;
-  float S = x.F[0] * b.y;
-  S = fmaf(x.F[1], b.z, S);
-  S = fmaf(x.F[K + 2], b.w, S);
-  float cc[K], e1[K], e2[K], h[K], E[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    cc[k] = fmaf(gz, x.d[k][2], fmaf(gy, x.d[k][1], gx * x.d[k][0]));
-    const float c2 = cc[k] * cc[k];
-    const float kp = LD ? a.w * x.dpar : a.w;
-    const float kq = LD ? b.x * x.dperp : b.x;
-    e1[k] = ex2(kp * c2);                 // exp(-b Dpar cos^2)
-    e2[k] = ex2(fmaf(-kq, c2, kq));       // exp(-b Dperp sin^2)
-    h[k] = fmaf(x.omf, e2[k], x.fin);     // f_intra + (1 - f_intra) e2
-    E[k] = e1[k] * h[k];                  // Eq. 5
-    S = fmaf(x.F[2 + k], E[k], S);        // Eq. 3
-  }
-  const float q = c.x * S;                // yhat - beta (B is in F)
-  const float yh = q + c.y;               // Eq. 6
-  // valid (0 for lanes past the end of the item) zeroes the lane's residual, so
-  // the loss, the per-measurement sums and the (unstored) adjoint all drop it
-  if (MODE == kMSE) {
-    const float r = (yh - yv) * valid;
-    seed = r;
-    t_loss = r * r;
-    t_sig = 0.0f;
-  } else {
-    const float ay = fabsf(yv), ah = fabsf(yh);
-    const float z = ay * ah * inv_s2;
-    float omr;
-    const float li = log_i0e(z, omr);
-    const float dd = ah - ay;
-    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li) * valid;
-    t_sig = fmaf(dd * dd, inv_s2, 2.0f * z * omr) * valid;
-    const float sd = fmaf(ay, omr, dd) * inv_s2 * valid;
-    seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
-  }
-  sq = seed * q;
-  acc.r[Acc<K, LD>::kLogB] += sq;
-  // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of fibre c's signal
-  const float dS = seed * c.x;
-  const float dSz = dS * c.z;             // dS (-2b), the factor of dE/dcos shared by the fibres
-  acc.r[0] = fmaf(dS, b.y, acc.r[0]);
-  acc.r[1] = fmaf(dS, b.z, acc.r[1]);
-  acc.r[K + 2] = fmaf(dS, b.w, acc.r[K + 2]);
-  float gfin = 0.0f;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    acc.r[2 + k] = fmaf(dS, E[k], acc.r[2 + k]);
-    const float e12 = e1[k] * e2[k];
-    gfin = fmaf(x.F[2 + k], e1[k] - e12, gfin);   // sum_k F_k dE_k/df_intra
-    // dE/dcos = cos e1 (-2b) (Dpar h - Dperp (1-fin) e2) = cos e1 (-2b) ((Dpar-Dperp) h + Dperp fin);
-    // the fibre's F_k multiplies the sums once per voxel, after the loop
-    const float t = fmaf(x.dpq, h[k], x.dqfin);
-    const float dc = (cc[k] * e1[k]) * t * dSz;
-    acc.r[Acc<K, LD>::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[Acc<K, LD>::kGd + 3 * k + 0]);
-    acc.r[Acc<K, LD>::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[Acc<K, LD>::kGd + 3 * k + 1]);
-    acc.r[Acc<K, LD>::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[Acc<K, LD>::kGd + 3 * k + 2]);
-    if (LD) {
-      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 e1 (1-fin) e2, with -b = (-2b)/2
-      const float dE = dS * x.F[2 + k];
-      const float mb = 0.5f * c.z;
-      const float c2 = cc[k] * cc[k];
-      acc.r[Acc<K, LD>::kDpar] = fmaf(dE * E[k], mb * c2, acc.r[Acc<K, LD>::kDpar]);
-      const float oe = x.omf * e2[k];
-      acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe, mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
-    }
-  }
-  acc.r[Acc<K, LD>::kFin] = fmaf(dS, gfin, acc.r[Acc<K, LD>::kFin]);
-}
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-// Measurements [nb, ne) for the VL voxels of this lane, in tiles of kTile.
-// The per-measurement sums over the wave's 64 x VL voxels (the alpha_n and
-// beta_n adjoints) are accumulated on the matrix core: with A = this lane's
-// partial and B = the one-hot column t = n - n0, v_mfma_f32_16x16x4f32 adds
-// each lane's value into column t of a 16x16 tile; after the tile, lane l
-// holds rows 4(l/16)..4(l/16)+3 of column l%16, so four adds and two lane
-// exchanges give the wave total for measurement n0 + l%16.  Invalid lanes
-// (beyond the item) carry valid = 0, which removes them from every sum.
-// FULL: every lane's voxels are in the item (the validity factors are 1 and
-// drop out at compile time).
-template <int K, int MODE, bool LD, int VL, bool FULL>
-__device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<K, LD> (&acc)[VL],
-                                                 const float* yg, int64_t V, const int (&vox)[VL],
-                                                 const float (&valid)[VL],
-                                                 const float4* __restrict__ acq,
-                                                 int nb, int ne, int N, float inv_s2, int lane,
-                                                 float* wacc, double& dloss, double& dsig) {
-  const int lane16 = lane & 15;
-  uint32_t voff[VL];  // byte offsets of the lane's voxels in a row of y
-#pragma unroll
-  for (int j = 0; j < VL; ++j) voff[j] = (uint32_t)vox[j] * 4u;
-  const uint32_t rowb = (uint32_t)V * 4u;  // bytes in a row of y (V <= 1023^3)
-  // y prefetch ring kPf measurements deep (slot u holds measurement nb + u mod kPf)
-  float yr[kPf][VL];
-#pragma unroll
-  for (int u = 0; u < kPf; ++u)
-#pragma unroll
-    for (int j = 0; j < VL; ++j) yr[u][j] = load_row_f32(yg + (int64_t)min(nb + u, ne - 1) * V, rowb, voff[j]);
-  v4f Da, Db;
-  float lacc, sacc;
-  float sel;  // one-hot over the 16 lanes of a row: 1 at lane16 == t (column t of the tile)
-  int n0 = nb;
-  // one measurement: the ring slot u is refilled (measurement n + kPf) only after
-  // its value has been consumed, so the load can target the slot's register
-  // directly and the wait for it lands kPf measurements later
-  auto body = [&](int t, float (&slot)[VL]) {
-    const int n = n0 + t;
-    const float4 a = acq[3 * n + 0];
-    const float4 b = acq[3 * n + 1];
-    const float4 c = acq[3 * n + 2];
-    float pa = 0.0f, pb = 0.0f;
-#pragma unroll
-    for (int j = 0; j < VL; ++j) {
-      float tl, ts, sq, sd;
-      pair<K, MODE, LD>(x[j], acc[j], slot[j], FULL ? 1.0f : valid[j], a, b, c, inv_s2, tl, ts, sq, sd);
-      lacc += tl;
-      if (MODE == kNLL) sacc += ts;
-      pa = j == 0 ? sq : pa + sq;
-      pb = j == 0 ? sd : pb + sd;
-    }
-    // refill from the measurement's row (a uniform base) at the lane's voxel
-    const float* row = yg + (int64_t)min(n + kPf, ne - 1) * V;  // clamped: in bounds
-#pragma unroll
-    for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
-    Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
-    Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    sel = dpp_f32<0x111>(sel);  // row_shr:1 moves the one to lane16 == t + 1
-  };
-  auto tile_begin = [&]() {
-    Da = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    Db = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    lacc = 0.0f;
-    sacc = 0.0f;
-    sel = lane16 == 0 ? 1.0f : 0.0f;
-  };
-  // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
-  auto group = [&](int t0) {
-#pragma unroll
-    for (int u = 0; u < kPf; ++u) {
-      body(t0 + u, yr[u]);
-      if ((u + 1) % sched_span(K, LD, VL) == 0) __builtin_amdgcn_sched_barrier(0);
-    }
-  };
-  // wave totals of the tile's per-measurement sums: lane l of the accumulator
-  // tile holds rows 4(l/16).. of column l%16
-  auto tile_end = [&](int cnt) {
-    float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);
-    float rb = (Db[0] + Db[1]) + (Db[2] + Db[3]);
-    ra += __shfl_xor(ra, 16, 64);
-    rb += __shfl_xor(rb, 16, 64);
-    ra += __shfl_xor(ra, 32, 64);
-    rb += __shfl_xor(rb, 32, 64);
-    if (lane < cnt) {
-      wacc[n0 + lane] += ra;
-      wacc[N + n0 + lane] += rb;
-    }
-    dloss += (double)lacc;
-    dsig += (double)sacc;
-  };
-  if (MODE == kMSE) {
-    // whole tiles: every path into the loop has the ring's loads in flight in slot
-    // order, so each wait is for exactly one slot
-    for (; n0 + kTile <= ne; n0 += kTile) {
-      tile_begin();
-#pragma unroll 1
-      for (int t0 = 0; t0 < kTile; t0 += kPf) group(t0);
-      tile_end(kTile);
-    }
-    if (n0 < ne) {  // the range's last, partial tile
-      const int cnt = ne - n0;
-      const int full = cnt - cnt % kPf;
-      tile_begin();
-#pragma unroll 1
-      for (int t0 = 0; t0 < full; t0 += kPf) group(t0);
-#pragma unroll
-      for (int u = 0; u + 1 < kPf; ++u)
-        if (full + u < cnt) body(full + u, yr[u]);
-      tile_end(cnt);
-    }
-  } else {
-    for (; n0 < ne; n0 += kTile) {
-      const int cnt = min(kTile, ne - n0);
-      tile_begin();
-      for (int t0 = 0; t0 < cnt; t0 += kPf) {
-#pragma unroll
-        for (int u = 0; u < kPf; ++u)
-          if (t0 + u < cnt) body(t0 + u, yr[u]);
-      }
-      tile_end(cnt);
-    }
-  }
-}
-
-// One Adam update (PyTorch's form) with step_size = lr / (1 - b1^t) and
-// ibc2 = 1 / sqrt(1 - b2^t); shared by k_adam and the fused pass so that both
-// give the same bits.
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float b1, float b2,
-                                         float eps, float step_size, float ibc2) {
-  m = fmaf(1.0f - b1, g - m, m);
-  v = fmaf(1.0f - b2, g * g, v * b2);
-  p = p - step_size * (m * rcp(fmaf(sqrt_hw(v), ibc2, eps)));
-}
-
-// Adam's step-dependent factors for t = step[0] + 1, in float64 as k_adam takes them
-__device__ __forceinline__ void adam_factors(const int32_t* step, float lr, float b1, float b2,
-                                             float& step_size, float& ibc2) {
-  // b1^t and b2^t by repeated squaring over the bits of t (a few float64
-  // multiplies where a general pow costs hundreds of instructions, on the
-  // thread that every wave of the fused pass's block waits for)
-  unsigned t = (unsigned)step[0] + 1u;
-  double p1 = 1.0, p2 = 1.0, x1 = (double)b1, x2 = (double)b2;
-  while (t) {
-    if (t & 1u) {
-      p1 *= x1;
-      p2 *= x2;
-    }
-    x1 *= x1;
-    x2 *= x2;
-    t >>= 1;
-  }
-  step_size = (float)((double)lr / (1.0 - p1));
-  ibc2 = (float)(1.0 / sqrt(1.0 - p2));
-}
-
-// statically sized LDS of the fused pass (one instance per kernel, shared by the
-// variants a persistent kernel inlines)
-constexpr int kRecVals = 18;  // per-thread record values of the fused pass
-struct PassShared {
-  double red[4][kRecVals];
-  double ep_d[2][kBlock];   // per-thread repulsion / sparsity partials
-  float ep_f[4][kBlock];    // per-thread orphan / continuity / ordering / TV partials
-  float ep_b[10][kBlock];   // per-thread quadratic-bias adjoint partials
-  float adam_sc[2];         // fused Adam: step size and 1/sqrt(1 - b2^t)
-};
-
-// The fused pass over one work item (a run of one group's voxels).
-template <int K, int MODE, bool LD, int VL>
-__device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __restrict__ acq_global,
-                                          const ItemDev& it, float4* smem4, PassShared& sh) {
-  auto& red = sh.red;
-  auto& ep_d = sh.ep_d;
-  auto& ep_f = sh.ep_f;
-  auto& ep_b = sh.ep_b;
-  constexpr int C = K + 3;
-  constexpr int NACC = Acc<K, LD>::N;
-  const GroupDev g = A.groups[it.group];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar)
-  const int WN = it.n_split, rows = 4 / WN;
-  const int row = wave / WN, split = wave - row * WN;
-  const int N = g.N;
-  float4* acq = smem4;                                       // [3N] unless read from SMEM
-  float* accab = reinterpret_cast<float*>(smem4 + (PRISM_ACQ_SMEM ? 0 : 3 * N));  // [4][2][N]
-  float* xbuf = accab + 8 * N;                               // [rows][WN-1][NACC][64*VL]
-
-#if PRISM_ACQ_SMEM
-  const float4* __restrict__ acq_tab = acq_global + g.acqtab_off / 4;
-#else
-  stage_acquisition(A, g, acq);
-  const float4* acq_tab = acq;
-#endif
-  for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
-  if (A.adam && tid == 0) adam_factors(A.step, A.lr, A.b1, A.b2, sh.adam_sc[0], sh.adam_sc[1]);
-  __syncthreads();
-
-  const int nb = (N * split) / WN, ne = (N * (split + 1)) / WN;
-  const int64_t V = g.V;
-  const float* yg = A.y + g.y_off;
-  const float* cal = A.th_cal + g.cal_off;
-  const float inv_s2 = MODE == kNLL ? expf(-2.0f * cal[g.n_bias + 2 * N]) : 0.0f;
-  const float sdata = MODE == kMSE ? 2.0f * g.invM : 1.0f;
-  const bool has_sp = (g.priors & kPriorSpatial) && g.nbh > 0;
-  float* wacc = accab + wave * 2 * N;
-
-  double dloss = 0.0, dsig = 0.0;
-  // per-thread partials of the epilogue (repulsion, sparsity, quadratic-bias adjoint),
-  // parked in LDS so that they are not live across the measurement loop
-  ep_d[0][tid] = 0.0;
-  ep_d[1][tid] = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ep_f[q][tid] = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 10; ++q) ep_b[q][tid] = 0.0f;
-  bool bad_grad = false, zero_dir = false;
-
-  const int chunk = 64 * VL * rows;
-  for (int cb = 0; cb < it.nv; cb += chunk) {
-    int vox[VL];
-    float valid[VL];
-#pragma unroll
-    for (int j = 0; j < VL; ++j) {
-      const int lv = cb + row * 64 * VL + j * 64 + lane;
-      const bool ok = lv < it.nv;
-      valid[j] = ok ? 1.0f : 0.0f;
-      vox[j] = it.v0 + (ok ? lv : 0);
-    }
-    Vox<K, LD> x[VL];
-    Acc<K, LD> acc[VL];
-#pragma unroll
-    for (int j = 0; j < VL; ++j) {
-      Derived dv_unused;
-      load_voxel<K, LD>(A, g, vox[j], x[j], dv_unused, zero_dir);
-#pragma unroll
-      for (int i = 0; i < NACC; ++i) acc[j].r[i] = 0.0f;
-    }
-
-    // a chunk that lies wholly inside the item runs the loop without validity factors
-    if (cb + chunk <= it.nv)
-      measurement_loop<K, MODE, LD, VL, true>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
-                                              wacc, dloss, dsig);
-    else
-      measurement_loop<K, MODE, LD, VL, false>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
-                                               wacc, dloss, dsig);
-
-    // combine the per-voxel accumulators of the waves that split this row over n
-    if (WN > 1) {
-      if (split > 0) {
-#pragma unroll
-        for (int j = 0; j < VL; ++j) {
-          float* dst = xbuf + (((row * (WN - 1) + split - 1) * NACC) * 64 * VL) + j * 64 + lane;
-#pragma unroll
-          for (int i = 0; i < NACC; ++i) dst[i * 64 * VL] = acc[j].r[i];
-        }
-      }
-      __syncthreads();
-      if (split == 0) {
-        for (int s = 1; s < WN; ++s) {
-#pragma unroll
-          for (int j = 0; j < VL; ++j) {
-            const float* src = xbuf + (((row * (WN - 1) + s - 1) * NACC) * 64 * VL) + j * 64 + lane;
-#pragma unroll
-            for (int i = 0; i < NACC; ++i) acc[j].r[i] += src[i * 64 * VL];
-          }
-        }
-      }
-    }
-
-    // epilogue: priors, chain rule to raw parameters, gradient store
-    if (split == 0) {
-      float* gm = A.g_micro + g.micro_off;
-      const float sc_rep = A.model.lam_rep * g.invM;
-      const float sc_spa = A.model.lam_sparse * g.invM;
-      const float sc_sp = A.model.lam_sp * g.invM;
-#pragma unroll
-      for (int j = 0; j < VL; ++j) {
-        if (valid[j] == 0.0f) continue;
-        const int v = vox[j];
-        Derived D;
-        {
-          Vox<K, LD> x_again;
-          bool zd = false;
-          load_voxel<K, LD>(A, g, v, x_again, D, zd);
-        }
-        float gF[C], gf[C];
-        float gS0 = 0.0f;
-        const float sB = sdata * D.B;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          gF[c] = sB * acc[j].r[c];
-          gf[c] = D.S0 * gF[c];
-          gS0 = fmaf(D.f[c], gF[c], gS0);
-        }
-        float gd[K][3];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float sF = sdata * x[j].F[2 + k];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) gd[k][a] = sF * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
-        }
-        if (has_sp) {
-          // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weights interleaved [V][cs]
-          constexpr int C4 = (C + 3) / 4;
-          const float4* w4 = reinterpret_cast<const float4*>(A.wsp + g.w_off);
-          const int32_t* nbr = A.nbr + g.nbr_off;
-          float4 sum[C4];
-#pragma unroll
-          for (int q = 0; q < C4; ++q) sum[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          int cnt = 0;
-          // six neighbours per round trip: their table entries, then their weight
-          // rows (an absent neighbour reads this voxel's row with factor 0)
-          constexpr int kNb = 6;
-          for (int q0 = 0; q0 < g.nbh; q0 += kNb) {
-            int u[kNb];
-#pragma unroll
-            for (int e = 0; e < kNb; ++e) u[e] = q0 + e < g.nbh ? nbr[(int64_t)(q0 + e) * V + v] : -1;
-            float4 t[kNb][C4];
-#pragma unroll
-            for (int e = 0; e < kNb; ++e) {
-              const int64_t src = (int64_t)(u[e] >= 0 ? u[e] : v) * C4;
-#pragma unroll
-              for (int i = 0; i < C4; ++i) t[e][i] = w4[src + i];
-            }
-#pragma unroll
-            for (int e = 0; e < kNb; ++e) {
-              const float on = u[e] >= 0 ? 1.0f : 0.0f;
-              cnt += u[e] >= 0 ? 1 : 0;
-#pragma unroll
-              for (int i = 0; i < C4; ++i) {
-                sum[i].x = fmaf(on, t[e][i].x, sum[i].x);
-                sum[i].y = fmaf(on, t[e][i].y, sum[i].y);
-                sum[i].z = fmaf(on, t[e][i].z, sum[i].z);
-                sum[i].w = fmaf(on, t[e][i].w, sum[i].w);
-              }
-            }
-          }
-          const float fc = (float)cnt;
-#pragma unroll
-          for (int i = 0; i < C4; ++i) {
-            const float4 t = w4[(int64_t)v * C4 + i];
-            const float own[4] = {t.x, t.y, t.z, t.w};
-            const float sm[4] = {sum[i].x, sum[i].y, sum[i].z, sum[i].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (4 * i + e < C) gf[4 * i + e] = fmaf(sc_sp, fmaf(own[e], fc, -sm[e]), gf[4 * i + e]);
-          }
-        }
-        if (g.priors & kPriorRep) {
-          float lr = 0.0f;
-#pragma unroll
-          for (int i = 0; i < K; ++i)
-#pragma unroll
-            for (int k = i + 1; k < K; ++k) {
-              const float dot = x[j].d[i][0] * x[j].d[k][0] + x[j].d[i][1] * x[j].d[k][1] +
-                                x[j].d[i][2] * x[j].d[k][2];
-              const float ad = fabsf(dot);
-              const float sg = dot > 0.0f ? 1.0f : (dot < 0.0f ? -1.0f : 0.0f);
-              const float fi = D.f[2 + i], fk = D.f[2 + k];
-              lr = fmaf(fi * fk, ad, lr);
-              gf[2 + i] = fmaf(sc_rep * fk, ad, gf[2 + i]);
-              gf[2 + k] = fmaf(sc_rep * fi, ad, gf[2 + k]);
-              const float w2 = sc_rep * fi * fk * sg;
-#pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                gd[i][a] = fmaf(w2, x[j].d[k][a], gd[i][a]);
-                gd[k][a] = fmaf(w2, x[j].d[i][a], gd[k][a]);
-              }
-            }
-          ep_d[0][tid] += (double)lr;
-        }
-        if (g.priors & kPriorSparse) {
-          float ls = 0.0f;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float fk = D.f[2 + k];
-            if (fk < A.model.tau_sparse) {
-              ls += fk;
-              gf[2 + k] += sc_spa;
-            }
-          }
-          ep_d[1][tid] += (double)ls;
-        }
-        if (g.priors & kPriorOrphan) {
-          // WM fractions where S0 is near zero: hinge max(0, 1 - S0/s0) on S0
-          const float s0o = A.model.s0_orphan;
-          const float sc = A.model.lam_orphan * g.invM;
-          const float h = fmaxf(0.0f, 1.0f - D.S0 / s0o);
-          float wsum = 0.0f;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            wsum += D.f[2 + k];
-            gf[2 + k] = fmaf(sc, h, gf[2 + k]);
-          }
-          if (D.S0 < s0o) gS0 -= (sc / s0o) * wsum;
-          ep_f[0][tid] += h * wsum;
-        }
-        if (g.priors & kPriorOrder) {
-          // fibre slots in descending order of fraction: hinge on each adjacent pair
-          const float sc = A.model.lam_order * g.invM;
-          float lo = 0.0f;
-#pragma unroll
-          for (int k = 0; k + 1 < K; ++k) {
-            const float gap = D.f[3 + k] - D.f[2 + k];
-            if (gap > 0.0f) {
-              lo += gap;
-              gf[3 + k] += sc;
-              gf[2 + k] -= sc;
-            }
-          }
-          ep_f[2][tid] += lo;
-        }
-        if ((g.priors & kPriorCont) && g.nbh > 0) {
-          // slot-wise alignment with the neighbours' directions; the pair (x, u)
-          // enters the sums of x and of u, weighted 1/|N(x)| and 1/|N(u)|
-          const int32_t* nbr = A.nbr + g.nbr_off;
-          const float* ninv = A.ninv + g.ninv_off;
-          const float* th = A.th_micro + g.micro_off;
-          const float sc2 = -2.0f * A.model.lam_cont * g.invM;
-          const float ax = ninv[v];
-          float lc = 0.0f;
-          for (int q = 0; q < g.nbh; ++q) {
-            const int u = nbr[(int64_t)q * V + v];
-            if (u < 0) continue;
-            const float w = sc2 * (ax + ninv[u]);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              const float ux = th[(int64_t)row_v(C, k, 0) * V + u];
-              const float uy = th[(int64_t)row_v(C, k, 1) * V + u];
-              const float uz = th[(int64_t)row_v(C, k, 2) * V + u];
-              const float n2 = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-              const float in = n2 > 0.0f ? rsq(n2) : 0.0f;
-              const float dx = ux * in, dy = uy * in, dz = uz * in;
-              const float dot = x[j].d[k][0] * dx + x[j].d[k][1] * dy + x[j].d[k][2] * dz;
-              lc = fmaf(ax, fmaf(-dot, dot, 1.0f), lc);
-              const float wd = w * dot;
-              gd[k][0] = fmaf(wd, dx, gd[k][0]);
-              gd[k][1] = fmaf(wd, dy, gd[k][1]);
-              gd[k][2] = fmaf(wd, dz, gd[k][2]);
-            }
-          }
-          ep_f[1][tid] += lc;
-        }
-        // softmax chain rule
-        float gsum = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) gsum = fmaf(D.f[c], gf[c], gsum);
-        float gout[4 * kMaxK + 7];
-        gout[0] = D.sig_s * gS0;
-#pragma unroll
-        for (int c = 0; c < C; ++c) gout[row_logit(c)] = D.f[c] * (gf[c] - gsum);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float pr = gd[k][0] * x[j].d[k][0] + gd[k][1] * x[j].d[k][1] + gd[k][2] * x[j].d[k][2];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            gout[row_v(C, k, a)] = (gd[k][a] - pr * x[j].d[k][a]) * D.invn[k];
-        }
-        gout[row_fin(C, K)] = x[j].fin * x[j].omf * sdata * acc[j].r[Acc<K, LD>::kFin];
-        if (LD) {
-          gout[row_dpar(C, K)] = D.sig_dpar * sdata * acc[j].r[Acc<K, LD>::kDpar];
-          gout[row_dpar(C, K) + 1] = D.sig_dperp * sdata * acc[j].r[Acc<K, LD>::kDperp];
-        }
-        constexpr int P = 4 * K + 5 + (LD ? 2 : 0);
-        if (A.adam) {
-          // fused Adam on this voxel's parameters (only this thread touches them)
-          const float ss = sh.adam_sc[0], ib = sh.adam_sc[1];
-          float* th = A.th_upd + g.micro_off;
-          float* mm = A.m_micro + g.micro_off;
-          float* vv = A.v_micro + g.micro_off;
-          // in two batches of parameters: each batch's loads are issued
-          // together so that their latencies overlap, in few registers
-          constexpr int kAdamBatch = (P + 1) / 2;
-#pragma unroll
-          for (int p0 = 0; p0 < P; p0 += kAdamBatch) {
-            float pp[kAdamBatch], m1[kAdamBatch], v1[kAdamBatch];
-#pragma unroll
-            for (int q = 0; q < kAdamBatch; ++q)
-              if (p0 + q < P) {
-                const int64_t i = (int64_t)(p0 + q) * V + v;
-                pp[q] = th[i];
-                m1[q] = mm[i];
-                v1[q] = vv[i];
-              }
-#pragma unroll
-            for (int q = 0; q < kAdamBatch; ++q)
-              if (p0 + q < P) {
-                const int p = p0 + q;
-                if (!isfinite(gout[p])) bad_grad = true;
-                const int64_t i = (int64_t)p * V + v;
-                adam_one(pp[q], gout[p], m1[q], v1[q], A.b1, A.b2, A.eps, ss, ib);
-                th[i] = pp[q];
-                mm[i] = m1[q];
-                vv[i] = v1[q];
-              }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-        } else {
-#pragma unroll
-          for (int p = 0; p < P; ++p) {
-            if (!isfinite(gout[p])) bad_grad = true;
-            gm[(int64_t)p * V + v] = gout[p];
-          }
-        }
-        // bias-field adjoint dL/dlogB(x)
-        float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
-        if ((g.priors & kPriorTV) && g.bias != 0) {
-          // |B(x+e_a) - B(x)| over the in-mask face pairs: x owns the pair toward +e_a
-          // and takes the derivative of both pairs it belongs to
-          const int32_t* nbr = A.nbr + g.nbr_off;
-          const float* cal = A.th_cal + g.cal_off;
-          const int32_t pc = A.coords[g.vox_off + v];
-          const float lb0 = log_bias(g, cal, pc);
-          const float B0 = D.B;
-          float lt = 0.0f, gt = 0.0f;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int32_t step = 1 << (10 * a);
-            if (nbr[(int64_t)(2 * a + 1) * V + v] >= 0) {
-              const float dl = log_bias(g, cal, pc + step) - lb0;
-              lt = fmaf(B0, fabsf(expm1f(dl)), lt);
-              gt += dl > 0.0f ? -B0 : (dl < 0.0f ? B0 : 0.0f);
-            }
-            if (nbr[(int64_t)(2 * a) * V + v] >= 0) {
-              const float dl = lb0 - log_bias(g, cal, pc - step);
-              gt += dl > 0.0f ? B0 : (dl < 0.0f ? -B0 : 0.0f);
-            }
-          }
-          glb = fmaf(A.model.lam_tv * g.invM, gt, glb);
-          ep_f[3][tid] += lt;
-        }
-        if (g.bias == 1) {
-          const int32_t pc = A.coords[g.vox_off + v];
-          const int i = pc & 1023, jj = (pc >> 10) & 1023, k = (pc >> 20) & 1023;
-          // the coordinates of log_bias, bit for bit
-          const float xx = fmaf((float)i, g.bsc[0], g.boff[0]);
-          const float yy = fmaf((float)jj, g.bsc[1], g.boff[1]);
-          const float zz = fmaf((float)k, g.bsc[2], g.boff[2]);
-          const float phi[10] = {1.0f, xx, yy, zz, xx * xx, yy * yy, zz * zz, xx * yy, xx * zz, yy * zz};
-#pragma unroll
-          for (int q = 0; q < 10; ++q) ep_b[q][tid] = fmaf(phi[q], glb, ep_b[q][tid]);
-        } else if (g.bias == 2) {
-          A.wsp[g.glb_off + v] = glb;
-        }
-      }
-    }
-    if (WN > 1) __syncthreads();  // xbuf is reused by the next chunk
-  }
-
-  // ---- item record: per-problem sums and per-measurement sums ----
-  double* rec = A.rec + g.rec_off + (int64_t)it.rec * g.rec_stride;
-  double vals[kRecVals];
-  vals[0] = dloss;
-  vals[1] = ep_d[0][tid];
-  vals[2] = ep_d[1][tid];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) vals[3 + q] = (double)ep_f[q][tid];
-  vals[7] = dsig;
-#pragma unroll
-  for (int q = 0; q < 10; ++q) vals[8 + q] = (double)ep_b[q][tid];
-#pragma unroll
-  for (int q = 0; q < kRecVals; ++q) {
-    const double s = wave_sum_f64(vals[q]);
-    if (lane == 0) red[wave][q] = s;
-  }
-  if (bad_grad) atomicOr(A.status, (uint32_t)kStNonfiniteGrad);
-  if (zero_dir) atomicOr(A.status, (uint32_t)kStZeroDir);
-  __syncthreads();
-  if (tid < kRecVals) {
-    const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    const int field = tid == 0 ? kRecData : tid == 1 ? kRecRep : tid == 2 ? kRecSparse
-                      : tid < 7 ? kRecOrphan + (tid - 3) : tid == 7 ? kRecSigma
-                      : kRecBias + (tid - 8);
-    rec[field] = s;
-  }
-  for (int n = tid; n < N; n += kBlock) {
-    rec[kRecAlpha + n] = (double)accab[n] + (double)accab[2 * N + n] + (double)accab[4 * N + n] +
-                         (double)accab[6 * N + n];
-    rec[kRecAlpha + N + n] = (double)accab[N + n] + (double)accab[3 * N + n] +
-                             (double)accab[5 * N + n] + (double)accab[7 * N + n];
-  }
-}
-
-// One block per item of one kernel variant.
-template <int K, int MODE, bool LD, int VL>
-__global__ __launch_bounds__(kBlock, pass_min_waves(K, LD, VL)) void k_pass(
-    PassArgs A, const float4* __restrict__ acq_global) {
-  extern __shared__ float4 smem4[];
-  __shared__ PassShared sh;
-  const ItemDev it = A.items[A.item_base + xcd_item(blockIdx.x, gridDim.x)];
-  pass_item<K, MODE, LD, VL>(A, acq_global, it, smem4, sh);
-}
-
-// Persistent launch over items of every variant: each block pops the next item
-// (largest first) from a device counter and runs that item's variant.  Every
-// block leaves the loop once the counter passes the last item.
-__device__ __forceinline__ int item_kind(int K, int mode, int ld) { return ((K - 1) * 2 + mode) * 2 + ld; }
-
-template <int K>
-__device__ __forceinline__ void dispatch_item(const PassArgs& A, const float4* __restrict__ acq_global,
-                                              const ItemDev& it, float4* smem4, PassShared& sh) {
-  switch (it.kind & 3) {
-    case 0: pass_item<K, kMSE, false, 1>(A, acq_global, it, smem4, sh); break;
-    case 1: pass_item<K, kMSE, true, 1>(A, acq_global, it, smem4, sh); break;
-    case 2: pass_item<K, kNLL, false, 1>(A, acq_global, it, smem4, sh); break;
-    default: pass_item<K, kNLL, true, 1>(A, acq_global, it, smem4, sh); break;
-  }
-}
-
-__global__ __launch_bounds__(kBlock, PRISM_PERSISTENT_MIN_WAVES) void k_pass_persistent(PassArgs A,
-                                                            const float4* __restrict__ acq_global,
-                                                            int32_t* counter) {
-  extern __shared__ float4 smem4[];
-  __shared__ PassShared sh;
-  __shared__ int next;
-  for (;;) {
-    __syncthreads();  // the previous item's LDS reads are done
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int i = next;
-    if (i >= A.n_items) break;
-    const ItemDev it = A.items[A.item_base + i];
-    switch ((it.kind >> 2) + 1) {
-      case 1: dispatch_item<1>(A, acq_global, it, smem4, sh); break;
-      case 2: dispatch_item<2>(A, acq_global, it, smem4, sh); break;
-      case 3: dispatch_item<3>(A, acq_global, it, smem4, sh); break;
-      case 4: dispatch_item<4>(A, acq_global, it, smem4, sh); break;
-      case 5: dispatch_item<5>(A, acq_global, it, smem4, sh); break;
-      default: dispatch_item<6>(A, acq_global, it, smem4, sh); break;
-    }
-  }
-}
-
-__global__ void k_counter_reset(int32_t* counter) {
-  if (threadIdx.x == 0) counter[0] = 0;
-}
-
-// ---------------------------------------------------------------------------
-// forward model only
-// ---------------------------------------------------------------------------
-template <int K, bool LD>
-__global__ __launch_bounds__(kBlock) void k_synth(PassArgs A) {
-  extern __shared__ float4 smem4[];
-  const ItemDev it = A.items[A.item_base + blockIdx.x];
-  const GroupDev g = A.groups[it.group];
-  float4* acq = smem4;
-  stage_acquisition(A, g, acq);
-  __syncthreads();
-  const int64_t V = g.V;
-  float* out = A.yhat + g.y_off;
-  bool zero_dir = false;
-  for (int lv = threadIdx.x; lv < it.nv; lv += kBlock) {
-    const int v = it.v0 + lv;
-    Vox<K, LD> x;
-    Derived dv;
-    load_voxel<K, LD>(A, g, v, x, dv, zero_dir);
-    for (int n = 0; n < g.N; ++n) {
-      const float4 a = acq[3 * n], b = acq[3 * n + 1], c = acq[3 * n + 2];
-      float S = x.F[0] * b.y;
-      S = fmaf(x.F[1], b.z, S);
-      S = fmaf(x.F[K + 2], b.w, S);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const float cc = fmaf(a.z, x.d[k][2], fmaf(a.y, x.d[k][1], a.x * x.d[k][0]));
-        const float c2 = cc * cc;
-        const float kp = LD ? a.w * x.dpar : a.w;
-        const float kq = LD ? b.x * x.dperp : b.x;
-        const float E = ex2(kp * c2) * (x.fin + x.omf * ex2(fmaf(-kq, c2, kq)));
-        S = fmaf(x.F[2 + k], E, S);
-      }
-      out[(int64_t)n * V + v] = fmaf(c.x, S, c.y);
-    }
-  }
-  if (zero_dir && A.status) atomicOr(A.status, (uint32_t)kStZeroDir);
-}
-
-// ---------------------------------------------------------------------------
-// Eq. 7 residual weights: w_c(x) = rho'(r_c(x)) / |N(x)|, r = f(x) - mean_N f
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void softmax_at(const float* th, int64_t V, int C, int v, float* f) {
-  float m = -INFINITY;
-#pragma unroll
-  for (int c = 0; c < kMaxC; ++c)
-    if (c < C) {
-      f[c] = th[(int64_t)(1 + c) * V + v];
-      m = fmaxf(m, f[c]);
-    }
-  float s = 0.0f;
-#pragma unroll
-  for (int c = 0; c < kMaxC; ++c)
-    if (c < C) {
-      f[c] = exp_hw(f[c] - m);
-      s += f[c];
-    }
-  const float inv = rcp(s);
-#pragma unroll
-  for (int c = 0; c < kMaxC; ++c)
-    if (c < C) f[c] *= inv;
-}
 
 // The two Eq. 7 kernels run one block per work item with up to kAuxBlock
 // threads, one voxel per thread (the launch sizes the block to the largest
@@ -1519,85 +511,17 @@ __global__ __launch_bounds__(256) void k_rprop(float* p, const float* g, float* 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// dynamic LDS: acquisition table, per-wave measurement sums and the cross-wave
-// buffer of the worst measurement split in the launch (xsplit = max rows*(WN-1): 0, 2 or 3)
-static size_t pass_lds_bytes(int maxN, int xsplit, int nacc_, int vpl) {
-  size_t b = (PRISM_ACQ_SMEM ? 0 : (size_t)maxN * 3 * sizeof(float4)) + (size_t)8 * maxN * sizeof(float);
-  b += (size_t)xsplit * nacc_ * 64 * vpl * sizeof(float);
-  return b;
-}
-
-template <int K, int MODE, bool LD, int VL>
-static hipError_t launch_pass_t(const PassArgs& a, hipStream_t s, int maxN) {
-  const size_t lds = pass_lds_bytes(maxN, a.n_split, (K + 3) + 3 * K + 2 + (LD ? 2 : 0), VL);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass<K, MODE, LD, VL>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  if (a.synth_only) {
-    hipLaunchKernelGGL((k_synth<K, LD>), dim3(a.n_items), dim3(kBlock),
-                       (size_t)maxN * 3 * sizeof(float4), s, a);
-  } else {
-    hipLaunchKernelGGL((k_pass<K, MODE, LD, VL>), dim3(a.n_items), dim3(kBlock), lds, s, a,
-                       reinterpret_cast<const float4*>(a.wsp));
-  }
-  return hipGetLastError();
-}
-
-template <int K>
-static hipError_t dispatch_mode(const PassArgs& a, int mode, int ld, int vpl, hipStream_t s,
-                                int maxN) {
-  if (vpl == 2) {
-    if (mode == kMSE) return ld ? launch_pass_t<K, kMSE, true, 2>(a, s, maxN) : launch_pass_t<K, kMSE, false, 2>(a, s, maxN);
-    return ld ? launch_pass_t<K, kNLL, true, 2>(a, s, maxN) : launch_pass_t<K, kNLL, false, 2>(a, s, maxN);
-  }
-  if (mode == kMSE) return ld ? launch_pass_t<K, kMSE, true, 1>(a, s, maxN) : launch_pass_t<K, kMSE, false, 1>(a, s, maxN);
-  return ld ? launch_pass_t<K, kNLL, true, 1>(a, s, maxN) : launch_pass_t<K, kNLL, false, 1>(a, s, maxN);
-}
-
 hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int vpl, int maxN,
                             hipStream_t s) {
   switch (K) {
-    case 1: return dispatch_mode<1>(a, mode, learn_d, vpl, s, maxN);
-    case 2: return dispatch_mode<2>(a, mode, learn_d, vpl, s, maxN);
-    case 3: return dispatch_mode<3>(a, mode, learn_d, vpl, s, maxN);
-    case 4: return dispatch_mode<4>(a, mode, learn_d, vpl, s, maxN);
-    case 5: return dispatch_mode<5>(a, mode, learn_d, vpl, s, maxN);
-    case 6: return dispatch_mode<6>(a, mode, learn_d, vpl, s, maxN);
+    case 1: return launch_pass_k<1>(a, mode, learn_d, vpl, maxN, s);
+    case 2: return launch_pass_k<2>(a, mode, learn_d, vpl, maxN, s);
+    case 3: return launch_pass_k<3>(a, mode, learn_d, vpl, maxN, s);
+    case 4: return launch_pass_k<4>(a, mode, learn_d, vpl, maxN, s);
+    case 5: return launch_pass_k<5>(a, mode, learn_d, vpl, maxN, s);
+    case 6: return launch_pass_k<6>(a, mode, learn_d, vpl, maxN, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
-                                  hipStream_t s) {
-  if (a.n_items <= 0) return hipSuccess;
-  const size_t lds = pass_lds_bytes(maxN, a.n_split, (kMaxK + 3) + 3 * kMaxK + 4, 1);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass_persistent,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, s, counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pass_persistent, dim3(grid), dim3(kBlock), lds, s, a,
-                     reinterpret_cast<const float4*>(a.wsp), counter);
-  return hipGetLastError();
-}
-
-int persistent_blocks_per_cu(int maxN, int xsplit) {
-  const size_t lds = pass_lds_bytes(maxN, xsplit, (kMaxK + 3) + 3 * kMaxK + 4, 1);
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_persistent, kBlock, lds) != hipSuccess) return 1;
-  return nb > 0 ? nb : 1;
-}
-
-hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {
-  // only the scalar-cache variant of k_pass reads the global table
-  if (n_groups <= 0 || !PRISM_ACQ_SMEM) return hipSuccess;
-  hipLaunchKernelGGL(k_stage, dim3(n_groups), dim3(256), 0, s, a);
-  return hipGetLastError();
 }
 
 hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, int max_nv, hipStream_t s) {

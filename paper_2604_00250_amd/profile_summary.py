@@ -40,7 +40,8 @@ def kernel_source_hash(root=None) -> str:
     import os
     here = root or os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha1()
-    for name in ("prism_kernels.hip", "prism_device.h", "prism_internal.h", "bessel_fit.h"):
+    names = sorted(n for n in os.listdir(here) if n.endswith((".hip", ".h")) and n != "microbench.hip")
+    for name in names:
         with open(os.path.join(here, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
