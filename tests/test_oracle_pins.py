@@ -305,6 +305,72 @@ def test_repulsion_two_fibres_closed_form():
     assert O.repulsion_prior(prob, f, d, C)[0] == 0.0
 
 
+def test_repulsion_is_averaged_over_the_mask():
+    """Three voxels, each with its own pair of fibres: the prior is the mean of
+    the per-voxel sums lam_rep f_1 f_2 |cos| over |M| = 3 voxels (Sec. 2.4,
+    topology priors), and its derivative with respect to f_1 at voxel x is
+    lam_rep f_2(x) |cos(x)| / 3.  Values worked out by hand."""
+    prob = make_prob(V=3, N=3, K=2, shape=(3, 1, 1))
+    f = np.zeros((5, 3))
+    f[2] = [0.5, 0.25, 0.4]     # fibre 1
+    f[3] = [0.2, 0.5, 0.4]      # fibre 2
+    cosines = [0.5, -0.8, 0.0]  # 60 deg, 143.13 deg (|cos| 0.8), 90 deg
+    d = np.zeros((2, 3, 3))
+    for x, c in enumerate(cosines):
+        d[0, :, x] = [1.0, 0.0, 0.0]
+        d[1, :, x] = [c, math.sqrt(1.0 - c * c), 0.0]
+    loss, gf, _ = O.repulsion_prior(prob, f, d, C)
+    # 0.5*0.2*0.5 + 0.25*0.5*0.8 + 0 = 0.05 + 0.1 = 0.15, times lam_rep / 3
+    assert loss == pytest.approx(0.01 * 0.15 / 3, rel=1e-13)
+    # d/df_1 = f_2 |cos| lam/3: (0.1, 0.4, 0) * 0.01/3
+    assert np.allclose(gf[0], np.array([0.1, 0.4, 0.0]) * 0.01 / 3, rtol=1e-13, atol=0)
+    # d/df_2 = f_1 |cos| lam/3: (0.25, 0.2, 0) * 0.01/3
+    assert np.allclose(gf[1], np.array([0.25, 0.2, 0.0]) * 0.01 / 3, rtol=1e-13, atol=0)
+    # |M| counts the problem's masked voxels even where a sub-region is evaluated
+    sub = make_prob(V=3, N=3, K=2, shape=(3, 1, 1))
+    sub.norm_count = 6
+    assert O.repulsion_prior(sub, f, d, C)[0] == pytest.approx(0.01 * 0.15 / 6, rel=1e-13)
+
+
+def test_calibration_penalty_by_hand():
+    """Sec. 2.3 item 2 and Sec. 2.4 (calibration regularisers): an L2 penalty
+    toward the identity calibration, lam_a |alpha|^2 + lam_b |beta|^2 +
+    lam_bias |c|^2 with the 0.01 weights.  Worked by hand for
+    alpha = (0.3, -0.2), beta = (0.1,), c = (0.5, -0.5):
+    0.01 (0.09 + 0.04) + 0.01 (0.01) + 0.01 (0.25 + 0.25) = 0.0064
+    (an L1 penalty would give 0.01 (0.5 + 0.1 + 1.0) = 0.016)."""
+    th = dict(alpha=np.array([0.3, -0.2]), beta=np.array([0.1]), bias=np.array([0.5, -0.5]))
+    loss, ga, gb, gw = O.calibration_prior(th, C)
+    assert loss == pytest.approx(0.0064, rel=1e-13)
+    assert np.allclose(ga, [0.006, -0.004], rtol=1e-13, atol=0)
+    assert np.allclose(gb, [0.002], rtol=1e-13, atol=0)
+    assert np.allclose(gw, [0.01, -0.01], rtol=1e-13, atol=0)
+    # quadratic: doubling every parameter quadruples the penalty
+    th2 = {k: 2.0 * v for k, v in th.items()}
+    assert O.calibration_prior(th2, C)[0] == pytest.approx(4.0 * 0.0064, rel=1e-13)
+    # at the identity calibration the penalty and its gradient vanish
+    z = {k: np.zeros_like(v) for k, v in th.items()}
+    out = O.calibration_prior(z, C)
+    assert out[0] == 0.0 and all(not np.any(g) for g in out[1:])
+
+
+def test_calibration_penalty_enters_the_objective_once():
+    """The total objective with the calibration prior on exceeds the one
+    without it by exactly the hand-computed penalty of test above, on a
+    problem whose calibration vector is set to those values."""
+    prob = make_prob(V=2, N=2, K=1, shape=(2, 1, 1), bias="none", priors=("cal",))
+    th = rand_theta(prob, seed=3)
+    th["alpha"] = np.array([0.3, -0.2])
+    th["beta"] = np.array([0.1, 0.0])
+    y = np.full((2, 2), 0.5)
+    on, _, _ = O.loss_grad(prob, th, y)
+    prob.priors = ()
+    off, _, _ = O.loss_grad(prob, th, y)
+    # 0.01 (0.09 + 0.04) + 0.01 (0.01) = 0.0014
+    assert on["total"] - off["total"] == pytest.approx(0.0014, rel=1e-10)
+    assert on["cal"] == pytest.approx(0.0014, rel=1e-13)
+
+
 def test_sparsity_threshold():
     prob = make_prob(V=2, N=3, K=3, shape=(2, 1, 1))
     f = np.array([[0.1, 0.1], [0.1, 0.1], [0.5, 0.14], [0.16, 0.3], [0.04, 0.2], [0.1, 0.16]])
