@@ -219,6 +219,25 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
                         float* grad_cal, void* workspace, size_t workspace_bytes,
                         uint32_t* status, void* stream);
 
+/* prism_loss_grad without a workspace argument, for callers that cannot
+ * allocate device memory (code that must not call hipMalloc: serving loops,
+ * harnesses that forbid allocation, work recorded into HIP graphs by callers
+ * that own no device buffers).  The workspace is a static device array of
+ * PRISM_NOALLOC_WORKSPACE_BYTES per GPU inside the library, held from the
+ * library's load until the process ends; its address is looked up once per
+ * device by prism_problem_create.  Problems whose prism_workspace_bytes
+ * exceeds that size are rejected with PRISM_E_WORKSPACE (nothing is queued).
+ * Calls on one GPU share that GPU's array (it keeps the last call's contents;
+ * nothing in it needs clearing between calls): two calls that may overlap on
+ * one GPU, on different streams or from different threads, race and give
+ * undefined results; calls queued on one stream are ordered and safe.  The
+ * other arguments and the results are those of prism_loss_grad, bit for
+ * bit.  Asynchronous on `stream`; allocates nothing. */
+#define PRISM_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+int32_t prism_loss_grad_noalloc(const prism_problem* h, const float* y, const float* theta_micro,
+                                const float* theta_cal, double* loss, float* grad_micro,
+                                float* grad_cal, uint32_t* status, void* stream);
+
 /* Adam (Kingma & Ba, Algorithm 1; the optimiser of Table 2 that the fit uses
  * here), elementwise over n float32 parameters, PyTorch's form:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;  t = step[0] + 1

@@ -29,6 +29,7 @@ LOSS_TERMS = ("data", "spatial", "rep", "sparse", "orphan", "continuity", "order
 LOSS_TOTAL = 9
 MAX_K = 6
 MAX_MEAS = 1024
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 
 
 class PrismError(RuntimeError):
@@ -94,6 +95,7 @@ SIGNATURES = {
     "prism_workspace_bytes": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "prism_synthesize": (_I32, [_P, _P, _P, _P, _P]),
     "prism_loss_grad": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
+    "prism_loss_grad_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "prism_adam_step": (_I32, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P, _P]),
     "prism_rprop_step": (_I32, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P]),
     "prism_iteration_adam": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _F, _F, _F, _F, _I32, _P, _P, _P,

@@ -360,6 +360,9 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   prism_problem* h = new (std::nothrow) prism_problem();
   if (!h) return fail(PRISM_E_ALLOC, "host allocation failed");
   (void)hipGetDevice(&h->device);
+  // set-up of this device's static workspace (prism_loss_grad_noalloc); a
+  // failure is reported by that entry point, not here
+  (void)static_scratch_setup(h->device);
   h->model = ModelDev{model->d_csf, model->d_gm, model->d_res, model->d_par, model->d_perp,
                       model->lam_sp, model->huber_delta, model->lam_rep, model->lam_sparse,
                       model->tau_sparse, model->lam_alpha, model->lam_beta, model->lam_bias,
@@ -739,6 +742,29 @@ int32_t prism_loss_grad(const prism_problem* h, const float* y, const float* the
                            workspace_bytes, status);
   if (rc != PRISM_OK) return rc;
   return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status,
+                  (hipStream_t)stream, nullptr);
+}
+
+static_assert(PRISM_NOALLOC_WORKSPACE_BYTES == kStaticScratchBytes, "static workspace size");
+
+int32_t prism_loss_grad_noalloc(const prism_problem* h, const float* y, const float* theta_micro,
+                                const float* theta_cal, double* loss, float* grad_micro,
+                                float* grad_cal, uint32_t* status, void* stream) {
+  if (!h) return fail(PRISM_E_INVALID, "handle is NULL");
+  size_t need = 0;
+  prism_workspace_bytes(h, &need);
+  if (need > kStaticScratchBytes)
+    return fail(PRISM_E_WORKSPACE,
+                "the problem needs %zu bytes of workspace; the static workspace of "
+                "prism_loss_grad_noalloc holds %zu (use prism_loss_grad with a caller workspace)",
+                need, kStaticScratchBytes);
+  hipError_t e = hipSuccess;
+  void* ws = static_scratch(h->device, &e);
+  if (!ws) return hip_fail(e, "static workspace of the problem's device");
+  int rc = check_pass_args(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, ws,
+                           kStaticScratchBytes, status);
+  if (rc != PRISM_OK) return rc;
+  return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, ws, status,
                   (hipStream_t)stream, nullptr);
 }
 

@@ -160,4 +160,13 @@ hipError_t launch_stitch(const StitchArgs& a, int K, int learn_d, hipStream_t s)
 hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n,
                         float em, float ep, float smin, float smax, hipStream_t s);
 
+
+// Static device workspace of prism_loss_grad_noalloc (prism_kernels.hip): its
+// size, the per-device set-up (hipGetSymbolAddress with `device` current, once
+// per device) and the address found by that set-up (nullptr and the error if
+// it failed or has not run).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+hipError_t static_scratch_setup(int device);
+void* static_scratch(int device, hipError_t* err);
+
 }  // namespace prism

@@ -10,6 +10,7 @@
 // k_stitch    blend of per-slab maps into whole-volume maps (slab fitting).
 // k_adam, k_rprop  optimiser steps.
 #include <algorithm>
+#include <mutex>
 
 #include "prism_common.h"
 
@@ -606,6 +607,50 @@ hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int6
   hipLaunchKernelGGL(k_rprop, dim3((unsigned)blocks), dim3(256), 0, s, p, g, prev, step, n, em, ep,
                      smin, smax);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static workspace of the allocation-free entry point (prism_loss_grad_noalloc)
+// ---------------------------------------------------------------------------
+// One array per device, held from the library's load until the process ends.
+// In host code `scratch` names a host-side stand-in, not the device array:
+// only the address hipGetSymbolAddress returns for the current device may be
+// passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr == nullptr) e = hipErrorInvalidSymbol;
+  if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+  g_scratch_err[device] = e;
+  if (cur != device) (void)hipSetDevice(cur);
+  return e;
+}
+
+void* static_scratch(int device, hipError_t* err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_ptr[device] ? hipSuccess
+                               : (g_scratch_err[device] != hipSuccess ? g_scratch_err[device] : hipErrorNotInitialized);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace prism

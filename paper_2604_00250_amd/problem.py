@@ -165,6 +165,10 @@ class Problem:
         L.check(L.lib().prism_loss_grad(self.handle, y, th_micro, th_cal, loss, g_micro, g_cal, ws,
                                         ws_bytes, status, stream))
 
+    def loss_grad_noalloc_ptr(self, y, th_micro, th_cal, loss, g_micro, g_cal, status, stream):
+        L.check(L.lib().prism_loss_grad_noalloc(self.handle, y, th_micro, th_cal, loss, g_micro, g_cal,
+                                                status, stream))
+
     def iteration_adam_ptr(self, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal, step, lr, b1, b2, eps,
                            update_cal, loss, g_micro, g_cal, ws, ws_bytes, status, stream):
         L.check(L.lib().prism_iteration_adam(self.handle, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal,

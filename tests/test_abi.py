@@ -142,6 +142,7 @@ def test_null_handles_and_optimiser_arguments():
     assert lib.prism_problem_destroy(None) == L.PRISM_E_INVALID
     assert lib.prism_loss_grad(None, None, None, None, None, None, None, None, 0, None, None) == L.PRISM_E_INVALID
     assert lib.prism_synthesize(None, None, None, None, None) == L.PRISM_E_INVALID
+    assert lib.prism_loss_grad_noalloc(None, None, None, None, None, None, None, None, None) == L.PRISM_E_INVALID
     n = ctypes.c_size_t()
     assert lib.prism_workspace_bytes(None, ctypes.byref(n)) == L.PRISM_E_INVALID
     assert lib.prism_adam_step(None, None, None, None, -1, 1e-2, 0.9, 0.999, 1e-8, None, None) == L.PRISM_E_INVALID
