@@ -5,17 +5,26 @@
 Workload: the whole-brain-shaped volume (145x174x145 grid, ~741k masked
 voxels, N = 288 three-shell measurements, K = 3, MSE mode, calibration on at
 identity, all priors), synthetic data from paper_2604_00250_amd.inputs.
-A step is one full iteration: the fused forward + adjoint pass with the
-spatial prior and the calibration reductions (prism_loss_grad) and the Adam
-update of every parameter (prism_adam_step), with y, parameters, moments and
-workspace resident in HBM.  Prints one JSON line.
+A step is one full iteration through prism_iteration_adam: the Eq. 7
+kernels, the fused forward + adjoint pass with the Adam update of every
+per-voxel parameter in its epilogue, the calibration reductions and the
+calibration vector's Adam update, with y, parameters, moments and workspace
+resident in HBM.  Prints one JSON line.
+
+Before the timed region (untimed): the roofline microbenchmark, --warmup
+iterations, then iterations for --warmup-seconds of wall time (the GPU's
+clocks ramp up over the first second or so of work).
 
 Extra legs (on by default, rank 0 only):
   roofline       fused-kernel time from HIP events recorded by the library
                  around each launch on the timed stream, against the VALU
                  issue roofline built from the microbenchmarked exp cost;
+  graph          the same iteration captured as a HIP graph and replayed;
+  fit            a whole fit of --fit-iterations graph-replayed iterations
+                 from the initial parameters (loss history, final MSE);
   cpu_baseline   the FP64 oracle on a bounded sample of the same volume, on
-                 the host cores (a process pool, one thread each);
+                 one host core and on the host cores (a process pool, one
+                 thread each), with the CPU model and core counts;
   torch_autograd the same objective written as plain per-op PyTorch FP32
                  autograd (+ torch.optim.Adam) on the same GPU.
 """
@@ -195,22 +204,50 @@ def _oracle_chunk(args):
     return hi - lo, time.perf_counter() - t
 
 
-def cpu_baseline(g, target_s=10.0, chunk=4096):
-    """The oracle's loss_grad over chunks of the volume's voxels, one process
-    per host core (each single-threaded), for about `target_s` seconds."""
-    import multiprocessing as mp
+def _cpu_model():
     try:
-        cores = len(os.sched_getaffinity(0))
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+# Worker processes of the all-core leg: the host cores this process may run on,
+# but at most one GPU's share of a shared host (16 cores per GPU on the boxes
+# this runs on), stated in the record as cpu_share.
+CPU_SHARE = 16
+
+
+def cpu_baseline(g, one_core_s=4.0, all_core_s=12.0, chunk=4096):
+    """The oracle's loss_grad over chunks of the volume's voxels, timed twice:
+    one process with one thread (1-core figure, about `one_core_s` seconds),
+    then one single-threaded process per core (all-core figure, about
+    `all_core_s` seconds of wall time, chunks cycling over the volume)."""
+    import multiprocessing as mp
+    visible = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        allowed = visible
+    cores = max(1, min(allowed, CPU_SHARE))
     _CPU_JOB["g"] = g
-    n, t1 = _oracle_chunk((0, chunk))     # calibrate one chunk in this process
-    per_chunk = t1
-    n_chunks = max(cores, int(target_s * cores / per_chunk))
     n_avail = max(1, g.n_vox // chunk)
-    # chunks cycle over the volume when the time budget asks for more than one pass
-    jobs = [((i % n_avail) * chunk, (i % n_avail + 1) * chunk) for i in range(n_chunks)]
+    # 1 core: chunks in this process, in order, until the time budget is spent
+    t = time.perf_counter()
+    vox1 = 0
+    i = 0
+    while time.perf_counter() - t < one_core_s or i == 0:
+        n, _ = _oracle_chunk(((i % n_avail) * chunk, (i % n_avail + 1) * chunk))
+        vox1 += n
+        i += 1
+    wall1 = time.perf_counter() - t
+    per_chunk = wall1 / i
+    # all cores: enough chunks for about all_core_s of wall time
+    n_chunks = max(cores, int(all_core_s * cores / per_chunk))
+    jobs = [((k % n_avail) * chunk, (k % n_avail + 1) * chunk) for k in range(n_chunks)]
     ctx = mp.get_context("fork")
     t = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -220,7 +257,10 @@ def cpu_baseline(g, target_s=10.0, chunk=4096):
     return dict(value=vox / wall, unit="voxel-iters/s", cores=cores, kind="oracle",
                 sample=f"{n_chunks} chunks x {chunk} voxels of the volume, cycling over its "
                        f"{n_avail} chunks ({vox} voxel-iterations of loss+gradient, N=288, K=3, FP64 "
-                       f"NumPy, one process per core), {wall:.1f} s wall",
+                       f"NumPy, one single-threaded process per core), {wall:.1f} s wall",
+                one_core=dict(value=vox1 / wall1, cores=1, chunks=i, seconds=wall1,
+                              sample=f"{i} chunks x {chunk} voxels in one single-threaded process"),
+                cpu_model=_cpu_model(), nproc=visible, cores_allowed=allowed, cpu_share=CPU_SHARE,
                 seconds_per_chunk_single_core=per_chunk)
 
 
@@ -302,16 +342,97 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def gpu_warmup(st, lr, seconds):
+    """Untimed iterations for a fixed wall time, whatever --warmup asks: the
+    GPU's clocks ramp up over the first second or so of sustained work."""
+    import torch
+    n = 0
+    t = time.perf_counter()
+    while True:
+        for _ in range(50):
+            st.iteration(lr=lr)
+        n += 50
+        torch.cuda.synchronize()
+        if time.perf_counter() - t >= seconds:
+            return dict(seconds=time.perf_counter() - t, iterations=n)
+
+
+def graph_leg(st, lr, steps):
+    """The same iteration captured once as a HIP graph and replayed `steps`
+    times (after a few untimed replays)."""
+    import torch
+    from paper_2604_00250_amd.fit import Loop, restore, snapshot
+    snap = snapshot(st)
+    loop = Loop(st, lr=lr)
+    loop.capture()
+    loop.replay(10)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loop.replay(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    restore(st, snap)
+    return e0.elapsed_time(e1) / steps
+
+
+def fit_leg(st, lr, iterations, N):
+    """A whole fit from the initial parameters with the iteration captured as a
+    HIP graph and replayed `iterations` times; the loss history stays on the
+    device until the end."""
+    import numpy as np
+    import torch
+    from paper_2604_00250_amd import _lib as L
+    from paper_2604_00250_amd.fit import Loop, restore, snapshot
+    snap = snapshot(st)
+    loop = Loop(st, lr=lr, history=iterations)
+    loop.capture()                    # runs one iteration on the way: start again from the snapshot
+    restore(st, snap)
+    loop.hist.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    loop.replay(iterations)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    hist = loop.hist[:, 0].cpu().numpy()             # [iterations][terms]
+    st.loss_grad()                                   # the loss at the final parameters
+    torch.cuda.synchronize()
+    final = st.loss_host()[0]
+    status = int(st.status.cpu().item())
+    marks = sorted({0, 1, 10, 100, 250, 500, iterations - 1} & set(range(iterations)))
+    data_i = L.LOSS_TERMS.index("data")
+    total = hist[:, L.LOSS_TOTAL]
+    best = float(total.min())
+    within = np.nonzero(total <= 1.01 * best)[0]
+    restore(st, snap)
+    return dict(iterations=iterations, ms_total=ms, ms_per_iteration=ms / iterations,
+                voxel_iters_per_s=None, loss_total={int(k): float(total[k]) for k in marks},
+                data_mse_per_measurement={int(k): float(hist[k, data_i] / N) for k in marks},
+                final_loss_total=float(final[L.LOSS_TOTAL]),
+                final_data_mse_per_measurement=float(final[data_i] / N),
+                first_iteration_within_1pct_of_best=int(within[0]) if within.size else None,
+                status=status)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup-seconds", type=float, default=2.0,
+                    help="untimed iterations for this long before the timed region, whatever --warmup is")
+    ap.add_argument("--fit-iterations", type=int, default=1000,
+                    help="graph-captured fit from the initial parameters (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-torch-baseline", action="store_true")
     ap.add_argument("--no-microbench", action="store_true")
     ap.add_argument("--no-fwd-adjoint", action="store_true",
                     help="skip the prism_loss_grad-only leg (counter runs see the timed kernel only)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--launch", type=str, default="", help="vox_per_lane,n_split,item_vox[,persistent]")
     ap.add_argument("--workload", choices=("brain", "batched"), default="brain",
                     help="brain: the 743k-voxel volume (the metric's configuration); batched: 4096 "
@@ -335,18 +456,30 @@ def main():
     # the CPU leg runs first, in worker processes forked before this process touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline(g)
     if cpu:
-        log(f"cpu baseline: {cpu['value']:.4g} voxel-iters/s on {cpu['cores']} cores")
+        log(f"cpu baseline: {cpu['value']:.4g} voxel-iters/s on {cpu['cores']} cores "
+            f"({cpu['one_core']['value']:.4g} on one)")
 
     import torch
     from paper_2604_00250_amd import _lib as L
+    from paper_2604_00250_amd.fit import restore, snapshot
     from paper_2604_00250_amd.problem import DeviceState, Problem
     launch = parse_launch(args.launch)
     prob = Problem([g], launch=launch)
     st = DeviceState(prob, ys=[g.y], thetas=[g.theta], device="cuda:0")
+    initial = snapshot(st)
     V = g.n_vox
 
+    # untimed GPU legs first: the roofline microbenchmark, then the fixed-duration warm-up
+    mb = None
+    if not args.no_microbench:
+        try:
+            from paper_2604_00250_amd import microbench
+            mb = microbench.run()
+        except Exception as ex:  # the roofline still reports with q = 1
+            log(f"microbenchmark failed: {ex}")
     for _ in range(args.warmup):
         st.iteration(lr=w.lr)
+    warm = gpu_warmup(st, w.lr, args.warmup_seconds) if args.warmup_seconds > 0 else None
     torch.cuda.synchronize()
     prob.profile(True, max_launches=args.steps + 4)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -378,15 +511,16 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_fa = e0.elapsed_time(e1) / args.steps
+    ms_graph = None if args.no_graph else graph_leg(st, w.lr, args.steps)
+    fit = None
+    if args.fit_iterations > 0:
+        restore(st, initial)
+        fit = fit_leg(st, w.lr, args.fit_iterations, g.acq.n)
+        fit["voxel_iters_per_s"] = V / (fit["ms_per_iteration"] * 1e-3)
+        log(f"fit: {fit['iterations']} graph-replayed iterations, {fit['ms_per_iteration']:.4f} ms each; "
+            f"loss {fit['loss_total']}")
 
     pairs = V * g.acq.n
-    mb = None
-    if not args.no_microbench:
-        try:
-            from paper_2604_00250_amd import microbench
-            mb = microbench.run()
-        except Exception as ex:  # the roofline still reports with q = 1
-            log(f"microbenchmark failed: {ex}")
     q = mb["q_exp"] if mb else 1.0
     slots = pairs * (ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR)
     achieved = slots / (k_ms * 1e-3)
@@ -417,7 +551,13 @@ def main():
         "config": {"workload": w.name, "voxels": V, "grid": list(g.shape), "measurements": g.acq.n,
                    "K": g.K, "mode": "mse", "priors": list(g.priors), "bias": g.bias,
                    "launch": prob.launch(), "step": "prism_iteration_adam (fused pass with the per-voxel Adam update, then Adam on the calibration)"},
+        "gpu_warmup": dict(warm or {}, microbench_first=mb is not None,
+                           note="untimed: the microbenchmark, then --warmup iterations, then iterations "
+                                "for --warmup-seconds of wall time, before the timed region"),
         "fwd_adjoint": {"value": V / (ms_fa * 1e-3), "ms": ms_fa} if ms_fa else None,
+        "graph": {"value": V / (ms_graph * 1e-3), "ms": ms_graph,
+                  "note": "the same iteration captured once as a HIP graph, replayed --steps times"}
+        if ms_graph else None,
         "roofline": roofline,
         "wall_s_timed": t_wall,
         "loss": float(loss[L.LOSS_TOTAL]),
@@ -425,6 +565,8 @@ def main():
         "paper_context": "~741k voxels x 100 iterations per slab in ~12 min on one RTX A6000 "
                          "(about 1e5 voxel-iters/s, MSE; a different machine and workload)",
     }
+    if fit:
+        out["fit"] = fit
     if mb:
         out["microbench"] = mb
     if not args.no_torch_baseline:
