@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PRISM_ABI_VERSION 2
+#define PRISM_ABI_VERSION 3
 #define PRISM_MAX_K 6
 #define PRISM_MAX_MEAS 1024
 #define PRISM_MAX_EDGE 1023
@@ -172,10 +172,23 @@ typedef struct {
                            multiple of 64 * vox_per_lane * 4 / n_split; 0 = automatic:
                            one block chunk (that multiple) with a fixed n_split, else
                            about six blocks per compute unit over the problem */
-  int32_t persistent;   /* 0: one launch per kernel variant (K, mode, learned D);
-                           1: one persistent launch over all work items, largest
-                           first, each block popping items from a device counter */
+  int32_t persistent;   /* 0: one launch per kernel variant (K, mode, learned D,
+                           voxels per lane); 1: one persistent launch over all work
+                           items, largest first, each block popping items from a
+                           device counter */
+  int32_t max_blocks;   /* persistent launch: at most this many blocks (0 = as many
+                           as the device holds at once); fewer blocks than work items
+                           make each block run several items in turn */
 } prism_launch;
+
+/* Launch shape of one bucket of groups: those with n_meas measurements, K
+ * fibre slots, data mode `mode` and learn_diffusivity.  Overrides the
+ * problem's vox_per_lane (ignored by the persistent launch), n_split and
+ * item_vox for the groups of that bucket. */
+typedef struct {
+  int32_t n_meas, K, mode, learn_diffusivity; /* the bucket */
+  int32_t vox_per_lane, n_split, item_vox;    /* as in prism_launch */
+} prism_bucket_launch;
 
 int32_t prism_abi_version(void);
 const char* prism_last_error(void);
@@ -192,9 +205,29 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
 int32_t prism_problem_destroy(prism_problem* h);
 int32_t prism_problem_info(const prism_problem* h, prism_problem_info_t* info);
 int32_t prism_group_info(const prism_problem* h, int32_t group, prism_group_info_t* info);
-/* Re-plan the work items for a launch shape; allocates, like create. */
+/* Re-plan the work items for a launch shape; allocates, like create.  On an
+ * invalid shape the previous plan is kept and PRISM_E_INVALID returned. */
 int32_t prism_problem_tune(prism_problem* h, const prism_launch* launch);
+/* As prism_problem_tune, with per-bucket shapes: buckets[0..n_buckets) each
+ * name a (n_meas, K, mode, learn_diffusivity) bucket present in the problem
+ * (at most once) and its shape; the other buckets take `launch`.  Replaces the
+ * overrides of an earlier call. */
+int32_t prism_problem_tune_buckets(prism_problem* h, const prism_launch* launch,
+                                   const prism_bucket_launch* buckets, int32_t n_buckets);
 int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch);
+/* The problem's buckets in order of first appearance among the groups, each
+ * with the shape its groups run with; *n receives the number of buckets, of
+ * which the first min(cap, *n) are written to out (host memory). */
+int32_t prism_problem_buckets(const prism_problem* h, prism_bucket_launch* out, int32_t cap,
+                              int32_t* n);
+/* The current plan: work items, fused-pass launches per call, and the grid of
+ * the persistent launch (0 when the plan is not persistent). */
+int32_t prism_problem_plan_info(const prism_problem* h, int32_t* n_items, int32_t* n_launches,
+                                int32_t* persistent_blocks);
+/* Hash of the sources the library was built from (a NUL-terminated string
+ * owned by the library), so that cached launch shapes and profiles can be
+ * tied to one build. */
+const char* prism_build_id(void);
 
 /* Bytes of device workspace prism_loss_grad needs (per-item partial sums and
  * the Eq. 7 residual weights).  The caller allocates it; contents need not be
@@ -307,6 +340,15 @@ int32_t prism_stitch_plan(prism_problem* h, int32_t nx, int32_t ny, int32_t nz, 
                           int64_t* n_out);
 int32_t prism_stitch_maps(const prism_problem* h, const float* theta_micro, float* maps,
                           void* stream);
+
+/* The Rician data term's special functions (Eq. 9) at arguments z >= 0, as
+ * the fused pass evaluates them: log_i0e[i] = log(I0(z) e^-z),
+ * one_minus_ratio[i] = 1 - I1(z)/I0(z) and q[i] = 2 z (1 - I1(z)/I0(z)) (the
+ * NLL adjoint and its sigma derivative use these).  Device arrays of n floats;
+ * asynchronous on `stream`.  For checking the approximation against a
+ * reference (its relative error is below 2e-7 over [0, 1e5]). */
+int32_t prism_rician_terms(const float* z, float* log_i0e, float* one_minus_ratio, float* q, int64_t n,
+                           void* stream);
 
 /* Optional per-kernel timing of the fused pass: when enabled, prism_loss_grad
  * records HIP events around each launch of the fused kernel on `stream`

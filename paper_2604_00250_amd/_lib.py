@@ -73,7 +73,13 @@ class ProblemInfo(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("vox_per_lane", ctypes.c_int32), ("n_split", ctypes.c_int32),
-                ("item_vox", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("item_vox", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int32)]
+
+
+class BucketLaunch(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("n_meas", "K", "mode", "learn_diffusivity", "vox_per_lane",
+                                               "n_split", "item_vox")]
 
 
 _P = ctypes.c_void_p
@@ -92,6 +98,10 @@ SIGNATURES = {
     "prism_group_info": (_I32, [_P, _I32, ctypes.POINTER(GroupInfo)]),
     "prism_problem_tune": (_I32, [_P, ctypes.POINTER(Launch)]),
     "prism_problem_launch": (_I32, [_P, ctypes.POINTER(Launch)]),
+    "prism_problem_tune_buckets": (_I32, [_P, ctypes.POINTER(Launch), ctypes.POINTER(BucketLaunch), _I32]),
+    "prism_problem_buckets": (_I32, [_P, ctypes.POINTER(BucketLaunch), _I32, ctypes.POINTER(_I32)]),
+    "prism_problem_plan_info": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "prism_build_id": (ctypes.c_char_p, []),
     "prism_workspace_bytes": (_I32, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "prism_synthesize": (_I32, [_P, _P, _P, _P, _P]),
     "prism_loss_grad": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -100,6 +110,7 @@ SIGNATURES = {
     "prism_rprop_step": (_I32, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P]),
     "prism_iteration_adam": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _F, _F, _F, _F, _I32, _P, _P, _P,
                                     _P, ctypes.c_size_t, _P, _P]),
+    "prism_rician_terms": (_I32, [_P, _P, _P, _P, _I64, _P]),
     "prism_stitch_plan": (_I32, [_P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int64)]),
     "prism_stitch_maps": (_I32, [_P, _P, _P, _P]),

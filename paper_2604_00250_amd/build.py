@@ -32,10 +32,25 @@ def hipcc():
     raise RuntimeError("hipcc not found (ROCm is required to build libprism)")
 
 
+def source_hash() -> str:
+    """SHA-1 (12 hex digits) of the library's sources: the csrc files and the C header."""
+    import hashlib
+    h = hashlib.sha1()
+    names = sorted(n for n in os.listdir(CSRC) if n.endswith((".hip", ".h", ".cpp")) and n != "microbench.hip")
+    for n in names:
+        h.update(n.encode())
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(HERE, "..", "include", "prism.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:12]
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     procs = []
-    flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    flags = [f"-DPRISM_SOURCE_HASH=\"{source_hash()}\"",
+             "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(HERE, "..", "include")]

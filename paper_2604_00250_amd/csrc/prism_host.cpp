@@ -17,6 +17,10 @@
 
 using namespace prism;
 
+#ifndef PRISM_SOURCE_HASH
+#define PRISM_SOURCE_HASH "unknown"
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -50,6 +54,7 @@ struct Bucket {
   int K, mode, learn_d, maxN;
   int item_begin, item_count;
   int xsplit;  // cross-wave buffer rows the launch needs
+  int vpl;     // voxels per lane of the launch (1 for the persistent launch)
 };
 
 }  // namespace
@@ -58,6 +63,7 @@ struct prism_problem {
   int device = 0;
   ModelDev model{};
   prism_launch launch{};
+  std::vector<prism_bucket_launch> bucket_launch;  // per-bucket overrides of `launch`
   std::vector<prism_group_desc> desc;       // mask pointers are not kept
   std::vector<GroupDev> groups;
   std::vector<ItemDev> items;
@@ -141,37 +147,53 @@ int item_split(const prism_launch& L, int nv) {
 
 int xsplit_of(int wn) { return (4 / wn) * (wn - 1); }  // cross-wave buffer rows
 
+// The launch shape of group g: the problem's shape with the overrides of the
+// group's bucket (N, K, mode, learned D), if any.  The persistent launch runs
+// one voxel per lane.
+prism_launch group_launch(const prism_problem* h, const GroupDev& g) {
+  prism_launch L = h->launch;
+  for (const prism_bucket_launch& b : h->bucket_launch)
+    if (b.n_meas == g.N && b.K == g.K && b.mode == g.mode && b.learn_diffusivity == g.learn_d) {
+      L.vox_per_lane = b.vox_per_lane;
+      L.n_split = b.n_split;
+      L.item_vox = b.item_vox;
+    }
+  if (L.persistent) L.vox_per_lane = 1;
+  return L;
+}
+
+// Voxels per work item of a group under its launch shape.
+int group_item_vox(const prism_problem* h, const prism_launch& L) {
+  const int vpl = L.vox_per_lane;
+  const int base_chunk = 64 * vpl * 4;  // voxels per block chunk with n_split = 1
+  if (L.item_vox > 0) return L.item_vox;
+  if (L.n_split > 0) {
+    // one block chunk per item: the finest cut balances the compute units
+    // best (brain-shaped volume, K = 3: 256-voxel items run the fused pass
+    // 2.4% faster than 512-voxel ones)
+    return 64 * vpl * (4 / L.n_split);
+  }
+  // split chosen per item: about six blocks per compute unit over the whole
+  // problem, whole chunks
+  const int64_t target = 256 * 6;
+  int64_t per = (h->n_vox + target - 1) / target;
+  per = ((per + base_chunk - 1) / base_chunk) * base_chunk;
+  return (int)std::max<int64_t>(base_chunk, std::min<int64_t>(per, 8 * base_chunk));
+}
+
 // Work items, launch buckets and reduction tiles for the current launch shape.
 int plan(prism_problem* h) {
   const prism_launch& L = h->launch;
-  const int vpl = L.persistent ? 1 : L.vox_per_lane;
-  const int base_chunk = 64 * vpl * 4;  // voxels per block chunk with n_split = 1
-  int item_vox = L.item_vox;
-  if (item_vox <= 0) {
-    if (L.n_split > 0) {
-      // one block chunk per item: the finest cut balances the compute units
-      // best (brain-shaped volume, K = 3: 256-voxel items run the fused pass
-      // 2.4% faster than 512-voxel ones)
-      item_vox = 64 * vpl * (4 / L.n_split);
-    } else {
-      // split chosen per item: about six blocks per compute unit over the
-      // whole problem, whole chunks
-      const int64_t target = 256 * 6;
-      int64_t per = (h->n_vox + target - 1) / target;
-      per = ((per + base_chunk - 1) / base_chunk) * base_chunk;
-      item_vox = (int)std::max<int64_t>(base_chunk, std::min<int64_t>(per, 8 * base_chunk));
-    }
-  }
-  if (L.n_split > 0 && item_vox % (64 * vpl * (4 / L.n_split)) != 0)
-    return fail(PRISM_E_INVALID, "item_vox %d is not a multiple of the block chunk %d", item_vox,
-                64 * vpl * (4 / L.n_split));
-
-  prism_launch Le = L;
-  Le.vox_per_lane = vpl;
   std::vector<ItemDev> items;
+  std::vector<int> item_vpl;
   std::vector<std::vector<int>> per_group(h->groups.size());
   for (size_t gi = 0; gi < h->groups.size(); ++gi) {
     GroupDev& g = h->groups[gi];
+    const prism_launch Lg = group_launch(h, g);
+    const int item_vox = group_item_vox(h, Lg);
+    if (Lg.n_split > 0 && item_vox % (64 * Lg.vox_per_lane * (4 / Lg.n_split)) != 0)
+      return fail(PRISM_E_INVALID, "group %d: item_vox %d is not a multiple of the block chunk %d", (int)gi,
+                  item_vox, 64 * Lg.vox_per_lane * (4 / Lg.n_split));
     int rec = 0;
     for (int v0 = 0; v0 < g.V; v0 += item_vox) {
       ItemDev it{};
@@ -179,10 +201,11 @@ int plan(prism_problem* h) {
       it.v0 = v0;
       it.nv = std::min(item_vox, g.V - v0);
       it.rec = rec++;
-      it.n_split = item_split(Le, it.nv);
+      it.n_split = item_split(Lg, it.nv);
       it.kind = ((g.K - 1) * 2 + g.mode) * 2 + g.learn_d;
       per_group[gi].push_back((int)items.size());
       items.push_back(it);
+      item_vpl.push_back(Lg.vox_per_lane);
     }
     g.item_count = rec;
   }
@@ -195,26 +218,27 @@ int plan(prism_problem* h) {
     ordered = items;
     std::stable_sort(ordered.begin(), ordered.end(),
                      [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
-    Bucket b{0, 0, 0, 0, 0, (int)ordered.size(), 0};
+    Bucket b{0, 0, 0, 0, 0, (int)ordered.size(), 0, 1};
     for (const ItemDev& it : ordered) {
       b.maxN = std::max(b.maxN, h->groups[it.group].N);
       b.xsplit = std::max(b.xsplit, xsplit_of(it.n_split));
     }
     if (b.item_count > 0) buckets.push_back(b);
   } else {
-    // one launch per kernel variant; items inside a bucket largest first (LPT)
-    std::vector<bool> done(h->groups.size(), false);
-    for (size_t gi = 0; gi < h->groups.size(); ++gi) {
-      if (done[gi]) continue;
-      const GroupDev& g0 = h->groups[gi];
-      Bucket b{g0.K, g0.mode, g0.learn_d, 0, (int)ordered.size(), 0, 0};
+    // one launch per kernel variant (K, mode, learned D, voxels per lane); items
+    // inside a launch largest first (LPT)
+    std::vector<bool> done(items.size(), false);
+    for (size_t i0 = 0; i0 < items.size(); ++i0) {
+      if (done[i0]) continue;
+      const GroupDev& g0 = h->groups[items[i0].group];
+      Bucket b{g0.K, g0.mode, g0.learn_d, 0, (int)ordered.size(), 0, 0, item_vpl[i0]};
       std::vector<ItemDev> bi;
-      for (size_t gj = gi; gj < h->groups.size(); ++gj) {
-        const GroupDev& g = h->groups[gj];
-        if (done[gj] || g.K != b.K || g.mode != b.mode || g.learn_d != b.learn_d) continue;
-        done[gj] = true;
+      for (size_t i = i0; i < items.size(); ++i) {
+        const GroupDev& g = h->groups[items[i].group];
+        if (done[i] || g.K != b.K || g.mode != b.mode || g.learn_d != b.learn_d || item_vpl[i] != b.vpl) continue;
+        done[i] = true;
         b.maxN = std::max(b.maxN, g.N);
-        for (int ii : per_group[gj]) bi.push_back(items[ii]);
+        bi.push_back(items[i]);
       }
       std::stable_sort(bi.begin(), bi.end(), [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
       for (const ItemDev& it : bi) b.xsplit = std::max(b.xsplit, xsplit_of(it.n_split));
@@ -263,7 +287,9 @@ int plan(prism_problem* h) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
       cus = 256;
     const int bpc = persistent_blocks_per_cu(buckets[0].maxN, buckets[0].xsplit);
-    h->persistent_grid = std::max(1, std::min((int)ordered.size(), cus * bpc));
+    int grid = std::min((int)ordered.size(), cus * bpc);
+    if (L.max_blocks > 0) grid = std::min(grid, L.max_blocks);
+    h->persistent_grid = std::max(1, grid);
   }
   hipError_t e = upload(&h->d_items, h->items);
   if (e == hipSuccess) e = upload(&h->d_tiles, h->tiles);
@@ -276,15 +302,43 @@ int plan(prism_problem* h) {
   return PRISM_OK;
 }
 
+int check_shape(int vpl, int n_split, int item_vox, const char* what) {
+  if (vpl != 1 && vpl != 2) return fail(PRISM_E_INVALID, "%s: vox_per_lane must be 1 or 2 (got %d)", what, vpl);
+  if (n_split != 0 && n_split != 1 && n_split != 2 && n_split != 4)
+    return fail(PRISM_E_INVALID, "%s: n_split must be 0 (per item), 1, 2 or 4 (got %d)", what, n_split);
+  if (item_vox < 0) return fail(PRISM_E_INVALID, "%s: item_vox must be >= 0", what);
+  return PRISM_OK;
+}
+
 int check_launch(const prism_launch* L) {
-  if (L->vox_per_lane != 1 && L->vox_per_lane != 2)
-    return fail(PRISM_E_INVALID, "vox_per_lane must be 1 or 2 (got %d)", L->vox_per_lane);
-  if (L->n_split != 0 && L->n_split != 1 && L->n_split != 2 && L->n_split != 4)
-    return fail(PRISM_E_INVALID, "n_split must be 0 (per item), 1, 2 or 4 (got %d)", L->n_split);
+  int rc = check_shape(L->vox_per_lane, L->n_split, L->item_vox, "launch");
+  if (rc != PRISM_OK) return rc;
   if (L->persistent != 0 && L->persistent != 1)
     return fail(PRISM_E_INVALID, "persistent must be 0 or 1");
-  if (L->item_vox < 0) return fail(PRISM_E_INVALID, "item_vox must be >= 0");
+  if (L->max_blocks < 0) return fail(PRISM_E_INVALID, "max_blocks must be >= 0");
   return PRISM_OK;
+}
+
+// The distinct (N, K, mode, learned D) buckets of a problem's groups, in order of first appearance.
+std::vector<prism_bucket_launch> bucket_signatures(const prism_problem* h) {
+  std::vector<prism_bucket_launch> out;
+  for (const GroupDev& g : h->groups) {
+    bool seen = false;
+    for (const prism_bucket_launch& b : out)
+      seen = seen || (b.n_meas == g.N && b.K == g.K && b.mode == g.mode && b.learn_diffusivity == g.learn_d);
+    if (seen) continue;
+    prism_bucket_launch b{};
+    b.n_meas = g.N;
+    b.K = g.K;
+    b.mode = g.mode;
+    b.learn_diffusivity = g.learn_d;
+    const prism_launch L = group_launch(h, g);
+    b.vox_per_lane = L.vox_per_lane;
+    b.n_split = L.n_split;
+    b.item_vox = L.item_vox;
+    out.push_back(b);
+  }
+  return out;
 }
 
 }  // namespace
@@ -513,6 +567,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   if (n_groups > 64) h->launch.n_split = 0;  // many groups: split per item size
   h->launch.item_vox = 0;
   h->launch.persistent = 0;
+  h->launch.max_blocks = 0;
   hipError_t e = upload(&h->d_bval, bval);
   if (e == hipSuccess) e = upload(&h->d_bvec, bvec);
   if (e == hipSuccess) e = upload(&h->d_coords, coords);
@@ -567,18 +622,46 @@ int32_t prism_group_info(const prism_problem* h, int32_t group, prism_group_info
   return PRISM_OK;
 }
 
-int32_t prism_problem_tune(prism_problem* h, const prism_launch* launch) {
+int32_t prism_problem_tune_buckets(prism_problem* h, const prism_launch* launch,
+                                   const prism_bucket_launch* buckets, int32_t n_buckets) {
   if (!h || !launch) return fail(PRISM_E_INVALID, "NULL argument");
+  if (n_buckets < 0 || (n_buckets > 0 && !buckets)) return fail(PRISM_E_INVALID, "bad bucket array");
   int rc = check_launch(launch);
   if (rc != PRISM_OK) return rc;
+  std::vector<prism_bucket_launch> bl(buckets, buckets + n_buckets);
+  for (int i = 0; i < n_buckets; ++i) {
+    const prism_bucket_launch& b = bl[i];
+    char what[96];
+    snprintf(what, sizeof(what), "bucket %d (N=%d, K=%d, mode %d, learned D %d)", i, b.n_meas, b.K, b.mode,
+             b.learn_diffusivity);
+    rc = check_shape(b.vox_per_lane, b.n_split, b.item_vox, what);
+    if (rc != PRISM_OK) return rc;
+    bool found = false;
+    for (const GroupDev& g : h->groups)
+      found = found || (b.n_meas == g.N && b.K == g.K && b.mode == g.mode && b.learn_diffusivity == g.learn_d);
+    if (!found) return fail(PRISM_E_INVALID, "%s: no group of the problem is in this bucket", what);
+    for (int j = 0; j < i; ++j)
+      if (bl[j].n_meas == b.n_meas && bl[j].K == b.K && bl[j].mode == b.mode &&
+          bl[j].learn_diffusivity == b.learn_diffusivity)
+        return fail(PRISM_E_INVALID, "%s is given twice", what);
+  }
   const prism_launch old = h->launch;
+  const std::vector<prism_bucket_launch> old_b = h->bucket_launch;
   h->launch = *launch;
+  h->bucket_launch = bl;
   rc = plan(h);
   if (rc != PRISM_OK) {
+    const std::string msg = g_last_error;
     h->launch = old;
+    h->bucket_launch = old_b;
     plan(h);
+    g_last_error = msg;
   }
   return rc;
+}
+
+int32_t prism_problem_tune(prism_problem* h, const prism_launch* launch) {
+  return prism_problem_tune_buckets(h, launch, nullptr, 0);
 }
 
 int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch) {
@@ -586,6 +669,26 @@ int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch) {
   *launch = h->launch;
   return PRISM_OK;
 }
+
+int32_t prism_problem_buckets(const prism_problem* h, prism_bucket_launch* out, int32_t cap, int32_t* n) {
+  if (!h || !n) return fail(PRISM_E_INVALID, "NULL argument");
+  if (cap < 0 || (cap > 0 && !out)) return fail(PRISM_E_INVALID, "bad output array");
+  const std::vector<prism_bucket_launch> b = bucket_signatures(h);
+  *n = (int32_t)b.size();
+  for (int i = 0; i < (int)b.size() && i < cap; ++i) out[i] = b[i];
+  return PRISM_OK;
+}
+
+int32_t prism_problem_plan_info(const prism_problem* h, int32_t* n_items, int32_t* n_launches,
+                                int32_t* persistent_blocks) {
+  if (!h || !n_items || !n_launches || !persistent_blocks) return fail(PRISM_E_INVALID, "NULL argument");
+  *n_items = (int32_t)h->items.size();
+  *n_launches = (int32_t)h->buckets.size();
+  *persistent_blocks = h->persistent_grid;
+  return PRISM_OK;
+}
+
+const char* prism_build_id(void) { return PRISM_SOURCE_HASH; }
 
 int32_t prism_workspace_bytes(const prism_problem* h, size_t* bytes) {
   if (!h || !bytes) return fail(PRISM_E_INVALID, "NULL argument");
@@ -689,7 +792,7 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     if (h->launch.persistent)
       e = launch_pass_persistent(a, b.maxN, h->persistent_grid, counter, s);
     else
-      e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, h->launch.vox_per_lane, b.maxN, s);
+      e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, b.vpl, b.maxN, s);
     if (e != hipSuccess) return hip_fail(e, "fused-pass launch");
     if (timed) {
       (void)hipEventRecord(h->ev[h->ev_used + 1], s);
@@ -832,6 +935,15 @@ int32_t prism_rprop_step(float* p, const float* g, float* prev, float* step, int
   hipError_t e = launch_rprop(p, g, prev, step, n, eta_minus, eta_plus, step_min, step_max,
                               (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "Rprop launch");
+  return PRISM_OK;
+}
+
+int32_t prism_rician_terms(const float* z, float* log_i0e, float* one_minus_ratio, float* q, int64_t n,
+                           void* stream) {
+  if (n < 0) return fail(PRISM_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!z || !log_i0e || !one_minus_ratio || !q)) return fail(PRISM_E_INVALID, "NULL device pointer");
+  hipError_t e = launch_rician_terms(z, log_i0e, one_minus_ratio, q, n, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "special-function launch");
   return PRISM_OK;
 }
 

@@ -160,6 +160,7 @@ hipError_t launch_stitch(const StitchArgs& a, int K, int learn_d, hipStream_t s)
 hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int64_t n,
                         float em, float ep, float smin, float smax, hipStream_t s);
 
+hipError_t launch_rician_terms(const float* z, float* li, float* omr, float* q, int64_t n, hipStream_t s);
 
 // Static device workspace of prism_loss_grad_noalloc (prism_kernels.hip): its
 // size, the per-device set-up (hipGetSymbolAddress with `device` current, once

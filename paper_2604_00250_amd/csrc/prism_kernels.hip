@@ -610,6 +610,28 @@ hipError_t launch_rprop(float* p, const float* g, float* prev, float* step, int6
 }
 
 // ---------------------------------------------------------------------------
+// the Eq. 9 special functions at given arguments, as the fused pass computes them
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rician_terms(const float* z, float* li, float* omr, float* q,
+                                                      int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float o, qq;
+    li[i] = log_i0e(z[i], o, qq);
+    omr[i] = o;
+    q[i] = qq;
+  }
+}
+
+hipError_t launch_rician_terms(const float* z, float* li, float* omr, float* q, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_rician_terms, dim3((unsigned)blocks), dim3(256), 0, s, z, li, omr, q, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Static workspace of the allocation-free entry point (prism_loss_grad_noalloc)
 // ---------------------------------------------------------------------------
 // One array per device, held from the library's load until the process ends.

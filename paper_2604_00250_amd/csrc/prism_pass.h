@@ -250,11 +250,11 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   } else {
     const float ay = fabsf(yv), ah = fabsf(yh);
     const float z = ay * ah * inv_s2;
-    float omr;
-    const float li = log_i0e(z, omr);
+    float omr, qz;
+    const float li = log_i0e(z, omr, qz);
     const float dd = ah - ay;
     t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li) * valid;
-    t_sig = fmaf(dd * dd, inv_s2, 2.0f * z * omr) * valid;
+    t_sig = fmaf(dd * dd, inv_s2, qz) * valid;  // qz = 2z (1 - R(z))
     const float sd = fmaf(ay, omr, dd) * inv_s2 * valid;
     seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
   }

@@ -83,15 +83,39 @@ class Problem:
         except Exception:
             pass
 
-    def tune(self, vox_per_lane=1, n_split=1, item_vox=0, persistent=0):
-        L.check(L.lib().prism_problem_tune(self.handle, ctypes.byref(
-            L.Launch(vox_per_lane, n_split, item_vox, int(persistent)))))
+    def tune(self, vox_per_lane=1, n_split=1, item_vox=0, persistent=0, max_blocks=0, buckets=()):
+        """Set the launch shape; `buckets` holds per-bucket overrides, dicts with
+        n_meas, K, mode ("mse"/"nll" or 0/1), learn_diffusivity, vox_per_lane,
+        n_split and item_vox."""
+        base = L.Launch(vox_per_lane, n_split, item_vox, int(persistent), int(max_blocks))
+        arr = (L.BucketLaunch * max(len(buckets), 1))()
+        for i, b in enumerate(buckets):
+            mode = b["mode"]
+            mode = L.RICIAN if mode in ("nll", L.RICIAN) else L.MSE
+            arr[i] = L.BucketLaunch(int(b["n_meas"]), int(b["K"]), mode, int(bool(b["learn_diffusivity"])),
+                                    int(b.get("vox_per_lane", 1)), int(b["n_split"]), int(b["item_vox"]))
+        L.check(L.lib().prism_problem_tune_buckets(self.handle, ctypes.byref(base), arr, len(buckets)))
 
     def launch(self) -> dict:
         ln = L.Launch()
         L.check(L.lib().prism_problem_launch(self.handle, ctypes.byref(ln)))
         return dict(vox_per_lane=ln.vox_per_lane, n_split=ln.n_split, item_vox=ln.item_vox,
-                    persistent=ln.persistent)
+                    persistent=ln.persistent, max_blocks=ln.max_blocks)
+
+    def buckets(self) -> list:
+        """The problem's (N, K, mode, learned D) buckets with the shape each runs with."""
+        n = ctypes.c_int32()
+        L.check(L.lib().prism_problem_buckets(self.handle, None, 0, ctypes.byref(n)))
+        arr = (L.BucketLaunch * max(n.value, 1))()
+        L.check(L.lib().prism_problem_buckets(self.handle, arr, n.value, ctypes.byref(n)))
+        return [dict(n_meas=b.n_meas, K=b.K, mode="nll" if b.mode == L.RICIAN else "mse",
+                     learn_diffusivity=bool(b.learn_diffusivity), vox_per_lane=b.vox_per_lane,
+                     n_split=b.n_split, item_vox=b.item_vox) for b in arr[:n.value]]
+
+    def plan_info(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(L.lib().prism_problem_plan_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(items=a.value, launches=b.value, persistent_blocks=c.value)
 
     def workspace_bytes(self) -> int:
         n = ctypes.c_size_t()

@@ -29,7 +29,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"binding misses {n}"
-    assert lib.prism_abi_version() == 2
+    assert lib.prism_abi_version() == 3
 
 
 def test_model_defaults_are_the_papers_constants():
