@@ -76,4 +76,59 @@ __device__ __forceinline__ void adam_factors(const int32_t* step, float lr, floa
   ibc2 = (float)(1.0 / sqrt(1.0 - p2));
 }
 
+// A voxel's row of the Eq. 7 buffers: [V][C] floats per group, the buffer
+// 16-byte aligned, so row v starts at float v C: read and written as float4
+// when C is a multiple of 4, float2 when C is even, single floats otherwise.
+// CT = 0 takes C at run time (launches over groups of different C).
+template <int CT>
+__device__ __forceinline__ void load_row(const float* __restrict__ base, int64_t v, int C,
+                                         float (&r)[CT ? CT : kMaxC]) {
+  if constexpr (CT == 0) {
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c) r[c] = c < C ? base[v * C + c] : 0.0f;
+  } else if constexpr (CT % 4 == 0) {
+    const float4* p = reinterpret_cast<const float4*>(base + v * CT);
+#pragma unroll
+    for (int i = 0; i < CT / 4; ++i) {
+      const float4 t = p[i];
+      r[4 * i] = t.x;
+      r[4 * i + 1] = t.y;
+      r[4 * i + 2] = t.z;
+      r[4 * i + 3] = t.w;
+    }
+  } else if constexpr (CT % 2 == 0) {
+    const float2* p = reinterpret_cast<const float2*>(base + v * CT);
+#pragma unroll
+    for (int i = 0; i < CT / 2; ++i) {
+      const float2 t = p[i];
+      r[2 * i] = t.x;
+      r[2 * i + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) r[c] = base[v * CT + c];
+  }
+}
+
+template <int CT>
+__device__ __forceinline__ void store_row(float* __restrict__ base, int64_t v, int C,
+                                          const float (&r)[CT ? CT : kMaxC]) {
+  if constexpr (CT == 0) {
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c)
+      if (c < C) base[v * C + c] = r[c];
+  } else if constexpr (CT % 4 == 0) {
+    float4* p = reinterpret_cast<float4*>(base + v * CT);
+#pragma unroll
+    for (int i = 0; i < CT / 4; ++i) p[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+  } else if constexpr (CT % 2 == 0) {
+    float2* p = reinterpret_cast<float2*>(base + v * CT);
+#pragma unroll
+    for (int i = 0; i < CT / 2; ++i) p[i] = make_float2(r[2 * i], r[2 * i + 1]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) base[v * CT + c] = r[c];
+  }
+}
+
 }  // namespace prism

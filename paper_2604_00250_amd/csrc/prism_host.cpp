@@ -72,7 +72,7 @@ struct prism_problem {
   std::vector<int32_t> tri_groups;
   std::vector<int32_t> acq_off;
   int max_field_chunks = 0;
-  int spatial_cs = 0;  // widest [V][cs] row of the groups with the Eq. 7 prior
+  int spatial_c = -1;  // C of every group with the Eq. 7 prior (-1: none yet, 0: they differ)
   int max_item_nv = 0;  // voxels of the plan's largest work item
   int persistent_grid = 0;
   int64_t n_vox = 0, n_micro = 0, n_cal = 0, n_y = 0;
@@ -532,12 +532,12 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
       grid.insert(grid.end(), idx.begin(), idx.end());
       h->tri_groups.push_back(gi);
     }
-    g.cs = (g.C + 3) & ~3;
-    wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned rows
-    g.w_off = wfl;  // [V][cs] residual weights, then [V][cs] fractions
+    wfl = (wfl + 3) & ~(int64_t)3;  // 16-byte aligned buffers
+    g.w_off = wfl;  // [V][C] residual weights, then [V][C] fractions
     if ((d.priors & PRISM_PRIOR_SPATIAL) && d.neighbourhood) {
-      wfl += 2 * (int64_t)g.cs * V;
-      h->spatial_cs = std::max(h->spatial_cs, g.cs);
+      wfl += 2 * (int64_t)g.C * V;
+      wfl = (wfl + 3) & ~(int64_t)3;
+      h->spatial_c = h->spatial_c < 0 ? g.C : (h->spatial_c == g.C ? g.C : 0);
     }
     g.glb_off = wfl;
     if (d.bias == PRISM_BIAS_TRILINEAR8) wfl += V;
@@ -780,7 +780,7 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
   if (!h->items.empty()) {
     a.item_base = 0;
     a.n_items = (int)h->items.size();
-    e = launch_spatial(a, (int)h->items.size(), h->spatial_cs, h->max_item_nv, s);
+    e = launch_spatial(a, (int)h->items.size(), std::max(h->spatial_c, 0), h->max_item_nv, s);
     if (e != hipSuccess) return hip_fail(e, "spatial-prior launch");
   }
   for (const Bucket& b : h->buckets) {

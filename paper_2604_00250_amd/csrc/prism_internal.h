@@ -11,7 +11,6 @@ constexpr int kBlock = 256;          // threads per block of the fused pass (4 w
 constexpr int kWave = 64;
 constexpr int kMaxK = 6;
 constexpr int kMaxC = kMaxK + 3;     // tissue compartments (csf, gm, wm_1..K, res)
-constexpr int kMaxCS = 12;           // kMaxC rounded up to a whole number of float4
 constexpr int kAcqStride = 12;       // floats per staged measurement
 constexpr int kRecHead = 19;         // record fields before alpha[N], beta[N]
 // record field indices (float64)
@@ -39,7 +38,7 @@ struct GroupDev {
   int64_t nbr_off;    // int32 offset of the neighbour table [ntab][V]; entries 0-5 are
                       // the face neighbours -x, +x, -y, +y, -z, +z, then the rest of 26
   int64_t ninv_off;   // float offset of 1/|N(x)| [V] (0 without neighbours)
-  int64_t w_off;      // float offset of the spatial weights [V][cs] in the workspace
+  int64_t w_off;      // float offset of the spatial weights [V][C], then fractions [V][C], in the workspace
   int64_t glb_off;    // float offset of per-voxel dL/dlogB [V] in the workspace (trilinear)
   int64_t rec_off;    // float64 offset of the group's first item record
   int64_t grid_off;   // int32 offset of the dense raster->voxel index grid (trilinear)
@@ -47,7 +46,6 @@ struct GroupDev {
   int32_t V, N, K, C, P;
   int32_t mode, bias, n_bias, learn_d, nbh, priors;
   int32_t ntab;       // neighbour-table entries (nbh, or 6 for the bias TV alone)
-  int32_t cs;         // per-voxel stride of the interleaved fractions / weights (C rounded up to 4)
   int32_t nx, ny, nz;
   float bsc[3], boff[3]; // quadratic bias coordinates xi_a = i_a bsc[a] + boff[a] in [-1, 1]
                          // (2/(n_a - 1) and -1; both 0 when n_a = 1)
@@ -138,9 +136,9 @@ struct StitchArgs {
 };
 
 // launchers (prism_kernels.hip)
-// max_cs: largest interleaved row width (cs) of the groups with the Eq. 7 prior, 0 if none
+// spatial_c: the C shared by every group with the Eq. 7 prior (0: none, or they differ)
 // max_nv: voxels of the largest work item
-hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, int max_nv, hipStream_t s);
+hipError_t launch_spatial(const PassArgs& a, int n_items, int spatial_c, int max_nv, hipStream_t s);
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
                                   hipStream_t s);

@@ -22,36 +22,36 @@ namespace prism {
 // table-then-gather loads of each voxel in turn.
 constexpr int kAuxBlock = 512;
 
-// fractions f = softmax(logits) once per voxel, interleaved [V][cs] (padding 0)
+// fractions f = softmax(logits) once per voxel, rows [V][C] (CT: see load_row)
+template <int CT>
 __global__ __launch_bounds__(kAuxBlock) void k_fractions(PassArgs A) {
   const ItemDev it = A.items[xcd_item(blockIdx.x, gridDim.x)];
   const GroupDev g = A.groups[it.group];
   if (!((g.priors & kPriorSpatial) && g.nbh > 0)) return;
   const float* th = A.th_micro + g.micro_off;
   const int64_t V = g.V;
-  const int C = g.C, C4 = g.cs / 4;
-  float4* f_out = reinterpret_cast<float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
+  const int C = CT ? CT : g.C;
+  float* f_out = A.wsp + g.w_off + (int64_t)C * V;
   for (int lv = threadIdx.x; lv < it.nv; lv += blockDim.x) {
     const int v = it.v0 + lv;
-    float f[kMaxCS];
+    float f[kMaxC];
     softmax_at(th, V, C, v, f);
+    float r[CT ? CT : kMaxC];
 #pragma unroll
-    for (int c = 0; c < kMaxCS; ++c)
-      if (c >= C) f[c] = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kMaxCS / 4; ++i)
-      if (i < C4) f_out[(int64_t)v * C4 + i] = make_float4(f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
+    for (int c = 0; c < (CT ? CT : kMaxC); ++c) r[c] = f[c];
+    store_row<CT>(f_out, v, C, r);
   }
 }
 
 // Eq. 7 residual weights w_c(x) = rho'(r_c(x)) / |N(x)| from the stored fractions.
 // Neighbours are taken six at a time: all six table entries are loaded, then
 // all their fraction rows (an absent neighbour reads the voxel's own row with
-// weight 0), so one round trip serves six neighbours.  C4M bounds the float4
-// columns of the rows (the launch takes the widest of the problem's groups).
-template <int C4M>
+// weight 0), so one round trip serves six neighbours.  CT is the launch's
+// common C, or 0 when its groups differ in C.
+template <int CT>
 __global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
   constexpr int kNb = 6;
+  constexpr int CM = CT ? CT : kMaxC;
   __shared__ double red[kAuxBlock / 64];
   const ItemDev it = A.items[xcd_item(blockIdx.x, gridDim.x)];
   const GroupDev g = A.groups[it.group];
@@ -60,57 +60,38 @@ __global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
   if ((g.priors & kPriorSpatial) && g.nbh > 0) {
     const int32_t* nbr = A.nbr + g.nbr_off;
     const int64_t V = g.V;
-    const int C = g.C, C4 = g.cs / 4;
-    const float4* fr = reinterpret_cast<const float4*>(A.wsp + g.w_off + (int64_t)g.cs * V);
-    float4* w_out = reinterpret_cast<float4*>(A.wsp + g.w_off);
+    const int C = CT ? CT : g.C;
+    const float* fr = A.wsp + g.w_off + (int64_t)C * V;
+    float* w_out = A.wsp + g.w_off;
     const float delta = A.model.huber_delta;
     for (int lv = tid; lv < it.nv; lv += blockDim.x) {
       const int v = it.v0 + lv;
-      float mean[4 * C4M];
+      float mean[CM];
 #pragma unroll
-      for (int c = 0; c < 4 * C4M; ++c) mean[c] = 0.0f;
+      for (int c = 0; c < CM; ++c) mean[c] = 0.0f;
       int cnt = 0;
       for (int q0 = 0; q0 < g.nbh; q0 += kNb) {
         int u[kNb];
 #pragma unroll
         for (int j = 0; j < kNb; ++j) u[j] = q0 + j < g.nbh ? nbr[(int64_t)(q0 + j) * V + v] : -1;
-        float4 t[kNb][C4M];
+        float t[kNb][CM];
 #pragma unroll
-        for (int j = 0; j < kNb; ++j) {
-          const int64_t src = (int64_t)(u[j] >= 0 ? u[j] : v) * C4;
-#pragma unroll
-          for (int i = 0; i < C4M; ++i)
-            if (i < C4) t[j][i] = fr[src + i];
-        }
+        for (int j = 0; j < kNb; ++j) load_row<CT>(fr, u[j] >= 0 ? u[j] : v, C, t[j]);
 #pragma unroll
         for (int j = 0; j < kNb; ++j) {
           const float on = u[j] >= 0 ? 1.0f : 0.0f;
           cnt += u[j] >= 0 ? 1 : 0;
 #pragma unroll
-          for (int i = 0; i < C4M; ++i)
-            if (i < C4) {
-              mean[4 * i] = fmaf(on, t[j][i].x, mean[4 * i]);
-              mean[4 * i + 1] = fmaf(on, t[j][i].y, mean[4 * i + 1]);
-              mean[4 * i + 2] = fmaf(on, t[j][i].z, mean[4 * i + 2]);
-              mean[4 * i + 3] = fmaf(on, t[j][i].w, mean[4 * i + 3]);
-            }
+          for (int c = 0; c < CM; ++c) mean[c] = fmaf(on, t[j][c], mean[c]);
         }
       }
-      float own[4 * C4M];
-#pragma unroll
-      for (int i = 0; i < C4M; ++i)
-        if (i < C4) {
-          const float4 t = fr[(int64_t)v * C4 + i];
-          own[4 * i] = t.x;
-          own[4 * i + 1] = t.y;
-          own[4 * i + 2] = t.z;
-          own[4 * i + 3] = t.w;
-        }
+      float own[CM];
+      load_row<CT>(fr, v, C, own);
       float ls = 0.0f;
       const float icnt = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
-      float w[4 * C4M];
+      float w[CM];
 #pragma unroll
-      for (int c = 0; c < 4 * C4M; ++c) {
+      for (int c = 0; c < CM; ++c) {
         w[c] = 0.0f;
         if (c < C && cnt > 0) {
           const float r = own[c] - mean[c] * icnt;
@@ -119,9 +100,7 @@ __global__ __launch_bounds__(kAuxBlock) void k_spatial(PassArgs A) {
           w[c] = (ar <= delta ? r : copysignf(delta, r)) * icnt;
         }
       }
-#pragma unroll
-      for (int i = 0; i < C4M; ++i)
-        if (i < C4) w_out[(int64_t)v * C4 + i] = make_float4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+      store_row<CT>(w_out, v, C, w);
       lsum += (double)ls;
     }
   }
@@ -525,20 +504,26 @@ hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int
   }
 }
 
-hipError_t launch_spatial(const PassArgs& a, int n_items, int max_cs, int max_nv, hipStream_t s) {
+template <int CT>
+static void launch_spatial_t(const PassArgs& a, dim3 grid, dim3 block, hipStream_t s) {
+  hipLaunchKernelGGL(k_fractions<CT>, grid, block, 0, s, a);
+  hipLaunchKernelGGL(k_spatial<CT>, grid, block, 0, s, a);
+}
+
+hipError_t launch_spatial(const PassArgs& a, int n_items, int spatial_c, int max_nv, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  // whole waves, one thread per voxel of the largest item, at most kAuxBlock
-  const dim3 grid(n_items), block(std::min(kAuxBlock, std::max(64, (max_nv + 63) / 64 * 64)));
+  // whole waves, one thread per voxel of the largest item, at most kAuxBlock;
   // k_spatial also writes each item's (zero) record when no group has the prior
-  hipLaunchKernelGGL(k_fractions, grid, block, 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (max_cs <= 4)
-    hipLaunchKernelGGL(k_spatial<1>, grid, block, 0, s, a);
-  else if (max_cs <= 8)
-    hipLaunchKernelGGL(k_spatial<2>, grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL(k_spatial<kMaxCS / 4>, grid, block, 0, s, a);
+  const dim3 grid(n_items), block(std::min(kAuxBlock, std::max(64, (max_nv + 63) / 64 * 64)));
+  switch (spatial_c) {
+    case 4: launch_spatial_t<4>(a, grid, block, s); break;
+    case 5: launch_spatial_t<5>(a, grid, block, s); break;
+    case 6: launch_spatial_t<6>(a, grid, block, s); break;
+    case 7: launch_spatial_t<7>(a, grid, block, s); break;
+    case 8: launch_spatial_t<8>(a, grid, block, s); break;
+    case 9: launch_spatial_t<9>(a, grid, block, s); break;
+    default: launch_spatial_t<0>(a, grid, block, s); break;
+  }
   return hipGetLastError();
 }
 

@@ -563,13 +563,12 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           for (int a = 0; a < 3; ++a) gd[k][a] = sF * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
         }
         if (has_sp) {
-          // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weights interleaved [V][cs]
-          constexpr int C4 = (C + 3) / 4;
-          const float4* w4 = reinterpret_cast<const float4*>(A.wsp + g.w_off);
+          // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weight rows [V][C]
+          const float* wrow = A.wsp + g.w_off;
           const int32_t* nbr = A.nbr + g.nbr_off;
-          float4 sum[C4];
+          float sum[C];
 #pragma unroll
-          for (int q = 0; q < C4; ++q) sum[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          for (int c = 0; c < C; ++c) sum[c] = 0.0f;
           int cnt = 0;
           // six neighbours per round trip: their table entries, then their weight
           // rows (an absent neighbour reads this voxel's row with factor 0)
@@ -578,36 +577,22 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
             int u[kNb];
 #pragma unroll
             for (int e = 0; e < kNb; ++e) u[e] = q0 + e < g.nbh ? nbr[(int64_t)(q0 + e) * V + v] : -1;
-            float4 t[kNb][C4];
+            float t[kNb][C];
 #pragma unroll
-            for (int e = 0; e < kNb; ++e) {
-              const int64_t src = (int64_t)(u[e] >= 0 ? u[e] : v) * C4;
-#pragma unroll
-              for (int i = 0; i < C4; ++i) t[e][i] = w4[src + i];
-            }
+            for (int e = 0; e < kNb; ++e) load_row<C>(wrow, u[e] >= 0 ? u[e] : v, C, t[e]);
 #pragma unroll
             for (int e = 0; e < kNb; ++e) {
               const float on = u[e] >= 0 ? 1.0f : 0.0f;
               cnt += u[e] >= 0 ? 1 : 0;
 #pragma unroll
-              for (int i = 0; i < C4; ++i) {
-                sum[i].x = fmaf(on, t[e][i].x, sum[i].x);
-                sum[i].y = fmaf(on, t[e][i].y, sum[i].y);
-                sum[i].z = fmaf(on, t[e][i].z, sum[i].z);
-                sum[i].w = fmaf(on, t[e][i].w, sum[i].w);
-              }
+              for (int c = 0; c < C; ++c) sum[c] = fmaf(on, t[e][c], sum[c]);
             }
           }
           const float fc = (float)cnt;
+          float own[C];
+          load_row<C>(wrow, v, C, own);
 #pragma unroll
-          for (int i = 0; i < C4; ++i) {
-            const float4 t = w4[(int64_t)v * C4 + i];
-            const float own[4] = {t.x, t.y, t.z, t.w};
-            const float sm[4] = {sum[i].x, sum[i].y, sum[i].z, sum[i].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (4 * i + e < C) gf[4 * i + e] = fmaf(sc_sp, fmaf(own[e], fc, -sm[e]), gf[4 * i + e]);
-          }
+          for (int c = 0; c < C; ++c) gf[c] = fmaf(sc_sp, fmaf(own[c], fc, -sum[c]), gf[c]);
         }
         if (g.priors & kPriorRep) {
           float lr = 0.0f;
