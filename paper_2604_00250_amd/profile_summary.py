@@ -117,6 +117,10 @@ def valu_summary(agent_csv, bench_json, out_md, kernel, commands, pass_csvs):
         ("VALU busy (fraction of SIMD-cycles)", busy_valu),
         ("matrix core busy (fraction of SIMD-cycles)", mfma),
         ("mean resident waves per SIMD", waves),
+        ("wave-cycles waiting for an instruction to issue (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES)",
+         c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"] if "SQ_WAIT_INST_ANY" in c else None),
+        ("wave-cycles waiting on a dependency or counter (SQ_WAIT_ANY / SQ_WAVE_CYCLES)",
+         c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"] if "SQ_WAIT_ANY" in c else None),
     ]
     with open(out_md, "w") as o:
         o.write(f"# VALU, transcendental and matrix-core use of {kernel} on {cfg['workload']}\n\n")
