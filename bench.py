@@ -292,6 +292,25 @@ def parse_launch(text):
     return dict(zip(keys, vals))
 
 
+def tuned_report(tuned):
+    """The autotuner's choices: the problem-wide shape with its time and the
+    runners-up, then each bucket's shape (an override where one beat the
+    problem-wide shape by more than 1%) with the best iteration time of its trials."""
+    out = {k: tuned[k] for k in ("launch", "cached", "ms", "build") if k in tuned}
+    if tuned.get("trials"):
+        out["problem_wide_trials"] = tuned["trials"]
+        out["best_problem_wide_ms"] = tuned["trials"][0]["ms"]
+    out["bucket_overrides"] = tuned.get("buckets", [])
+    per = {}
+    for t in tuned.get("bucket_trials", []):
+        b = per.setdefault(t["bucket"], dict(trials=0, best_ms=float("inf"), best_shape=None))
+        b["trials"] += 1
+        if t["ms"] < b["best_ms"]:
+            b["best_ms"], b["best_shape"] = t["ms"], t["shape"]
+    out["bucket_search"] = per
+    return out
+
+
 def bench_batched(args):
     """4096 independent patches of uneven size (edge log-uniform 4-24), N in
     {33, 96, 288}, K in 1..5, MSE or NLL, in one problem; the launch shape comes
@@ -313,10 +332,11 @@ def bench_batched(args):
         tuned = dict(launch=launch, cached=False)
     else:
         tuned = autotune(st, cache=None, reps=3)
-        log(f"autotuner: {tuned['launch']} ({tuned['ms']:.3f} ms); "
+        log(f"autotuner: {tuned['launch']} ({tuned['ms']:.3f} ms with {len(tuned['buckets'])} bucket overrides); "
             + "; ".join(f"{t['launch']}: {t['ms']:.3f}" for t in tuned["trials"]))
     for _ in range(args.warmup):
         st.iteration(lr=w.lr)
+    warm = gpu_warmup(st, w.lr, args.warmup_seconds) if args.warmup_seconds > 0 else None
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -335,8 +355,8 @@ def bench_batched(args):
         "config": {"workload": w.name, "patches": len(w.groups), "voxels": V, "pairs": pairs,
                    "launch": prob.launch(), "step": "prism_iteration_adam (fused pass with the per-voxel Adam update, then Adam on the calibration)"},
         "pairs_per_s": pairs / (ms * 1e-3),
-        "autotune": {k: tuned[k] for k in ("launch", "cached") if k in tuned} | (
-            {"trials": tuned["trials"]} if "trials" in tuned else {}),
+        "autotune": tuned_report(tuned),
+        "gpu_warmup": warm,
         "status": int(st.status.cpu().item()),
     }
     print(json.dumps(out), flush=True)

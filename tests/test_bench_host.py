@@ -41,3 +41,20 @@ def test_stored_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     # a different source hash voids the stored figure
     monkeypatch.setattr(ps, "kernel_source_hash", lambda root=None: "000000000000")
     assert bench.stored_traffic("brain145x174x145_n288_k3_mse") is None
+
+
+def test_tuned_report_lists_bucket_choices_and_best_trial_times():
+    import bench
+    tuned = dict(launch=dict(vox_per_lane=1, n_split=0, item_vox=0, persistent=1), ms=7.5, cached=False,
+                 trials=[dict(launch="a", ms=7.8), dict(launch="b", ms=9.0)],
+                 buckets=[dict(n_meas=288, K=3, mode="mse", learn_diffusivity=False, vox_per_lane=1, n_split=1,
+                               item_vox=512)],
+                 bucket_trials=[dict(bucket="N288_K3_mse_fixedD", shape=dict(n_split=1, item_vox=512), ms=7.5),
+                                dict(bucket="N288_K3_mse_fixedD", shape=dict(n_split=2, item_vox=256), ms=7.9),
+                                dict(bucket="N33_K1_nll_fixedD", shape=dict(n_split=4, item_vox=64), ms=7.8)])
+    r = bench.tuned_report(tuned)
+    assert r["best_problem_wide_ms"] == 7.8 and r["ms"] == 7.5
+    assert r["bucket_overrides"] == tuned["buckets"]
+    b = r["bucket_search"]["N288_K3_mse_fixedD"]
+    assert b["trials"] == 2 and b["best_ms"] == 7.5 and b["best_shape"] == dict(n_split=1, item_vox=512)
+    assert r["bucket_search"]["N33_K1_nll_fixedD"]["trials"] == 1
