@@ -55,13 +55,15 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
   p = p - step_size * (m * rcp(fmaf(sqrt_hw(v), ibc2, eps)));
 }
 
-// Adam's step-dependent factors for t = step[0] + 1, in float64 as k_adam takes them
+// Adam's step-dependent factors for t = step[0] + 1 (t = step[0] when the
+// counter was advanced earlier in the same call: ready = 1), in float64 as
+// k_adam takes them
 __device__ __forceinline__ void adam_factors(const int32_t* step, float lr, float b1, float b2,
-                                             float& step_size, float& ibc2) {
+                                             float& step_size, float& ibc2, int ready = 0) {
   // b1^t and b2^t by repeated squaring over the bits of t (a few float64
   // multiplies where a general pow costs hundreds of instructions, on the
   // thread that every wave of the fused pass's block waits for)
-  unsigned t = (unsigned)step[0] + 1u;
+  unsigned t = (unsigned)step[0] + (ready ? 0u : 1u);
   double p1 = 1.0, p2 = 1.0, x1 = (double)b1, x2 = (double)b2;
   while (t) {
     if (t & 1u) {

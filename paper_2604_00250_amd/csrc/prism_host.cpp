@@ -693,7 +693,8 @@ const char* prism_build_id(void) { return PRISM_SOURCE_HASH; }
 int32_t prism_workspace_bytes(const prism_problem* h, size_t* bytes) {
   if (!h || !bytes) return fail(PRISM_E_INVALID, "NULL argument");
   *bytes = align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)) +
-           align256(h->ws_float * sizeof(float)) + 256;  // + the persistent launch's item counter
+           align256(h->ws_float * sizeof(float)) + align256(h->groups.size() * 3 * sizeof(double)) +
+           256;  // + the persistent launch's item counter
   return PRISM_OK;
 }
 
@@ -753,17 +754,37 @@ namespace {
 
 // Workspace carve-up and the pass: Eq. 7 weights, fused pass, reductions, the
 // trilinear bias adjoint.  `adam` (optional) turns on the fused update of the
-// per-voxel parameters in the pass epilogue.
+// per-voxel parameters in the pass epilogue; with `cal_adam` also set, the
+// calibration vector is updated where its gradient is written (k_reduce2,
+// k_bias_tri) and the step counter advances in the call's first kernel.
+struct CalAdam {
+  float* th;
+  float* m;
+  float* v;
+  int32_t* step;
+  float lr, b1, b2, eps;
+  int update;  // 0: theta_cal held fixed (the counter still advances)
+};
+
 int run_pass(const prism_problem* h, const float* y, const float* theta_micro, const float* theta_cal,
              double* loss, float* grad_micro, float* grad_cal, void* workspace, uint32_t* status,
-             hipStream_t s, const PassArgs* adam) {
+             hipStream_t s, const PassArgs* adam, const CalAdam* cal_adam = nullptr) {
   char* ws = (char*)workspace;
+  const size_t o_part = align256(h->ws_rec * sizeof(double));
+  const size_t o_float = o_part + align256(h->ws_part * sizeof(double));
+  const size_t o_calsq = o_float + align256(h->ws_float * sizeof(float));
+  const size_t o_counter = o_calsq + align256(h->groups.size() * 3 * sizeof(double));
   double* rec = (double*)ws;
-  double* part = (double*)(ws + align256(h->ws_rec * sizeof(double)));
-  float* wsp = (float*)(ws + align256(h->ws_rec * sizeof(double)) + align256(h->ws_part * sizeof(double)));
-  int32_t* counter = (int32_t*)(ws + align256(h->ws_rec * sizeof(double)) +
-                                align256(h->ws_part * sizeof(double)) + align256(h->ws_float * sizeof(float)));
+  double* part = (double*)(ws + o_part);
+  float* wsp = (float*)(ws + o_float);
+  double* calsq = (double*)(ws + o_calsq);
+  int32_t* counter = (int32_t*)(ws + o_counter);
+  const bool have_items = !h->items.empty();
   PassArgs a = pass_args(h, y, theta_micro, theta_cal, grad_micro, rec, wsp, status);
+  a.n_groups = (int)h->groups.size();
+  // the calibration prior's sums of squares come from the call's first kernel
+  // (before any parameter changes) whenever there is one
+  a.calsq = have_items ? calsq : nullptr;
   if (adam) {
     a.adam = 1;
     a.th_upd = adam->th_upd;
@@ -774,6 +795,10 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     a.b1 = adam->b1;
     a.b2 = adam->b2;
     a.eps = adam->eps;
+    if (cal_adam) {
+      a.step_advance = cal_adam->step;
+      a.step_ready = 1;
+    }
   }
   hipError_t e = launch_stage(a, (int)h->groups.size(), s);
   if (e != hipSuccess) return hip_fail(e, "acquisition staging launch");
@@ -781,6 +806,7 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     a.item_base = 0;
     a.n_items = (int)h->items.size();
     e = launch_spatial(a, (int)h->items.size(), std::max(h->spatial_c, 0), h->max_item_nv, s);
+    a.step_advance = nullptr;  // advanced once, by the first kernel
     if (e != hipSuccess) return hip_fail(e, "spatial-prior launch");
   }
   for (const Bucket& b : h->buckets) {
@@ -814,6 +840,18 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
   r.model = h->model;
   r.n_tiles = (int)h->tiles.size();
   r.n_groups = (int)h->groups.size();
+  r.calsq = a.calsq;
+  if (cal_adam && cal_adam->update) {
+    r.cal_adam = 1;
+    r.th_cal_upd = cal_adam->th;
+    r.m_cal = cal_adam->m;
+    r.v_cal = cal_adam->v;
+    r.step = cal_adam->step;
+    r.lr = cal_adam->lr;
+    r.b1 = cal_adam->b1;
+    r.b2 = cal_adam->b2;
+    r.eps = cal_adam->eps;
+  }
   e = launch_reduce(r, h->max_field_chunks, s);
   if (e != hipSuccess) return hip_fail(e, "reduction launch");
   e = launch_bias_trilinear(r, h->d_tri, (int)h->tri_groups.size(), s);
@@ -888,6 +926,22 @@ int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* thet
   bool fuse = true;  // the continuity prior reads neighbours' parameters during the pass
   for (const GroupDev& g : h->groups)
     if ((g.priors & PRISM_PRIOR_CONTINUITY) && g.nbh > 0) fuse = false;
+  if (fuse && !h->items.empty()) {
+    // one call: the step counter advances in the first kernel, the per-voxel
+    // parameters are updated in the fused pass, the calibration vector where
+    // its gradient is written
+    PassArgs ad{};
+    ad.th_upd = theta_micro;
+    ad.m_micro = m_micro;
+    ad.v_micro = v_micro;
+    ad.step = step;
+    ad.lr = lr;
+    ad.b1 = beta1;
+    ad.b2 = beta2;
+    ad.eps = eps;
+    CalAdam ca{theta_cal, m_cal, v_cal, step, lr, beta1, beta2, eps, update_cal ? 1 : 0};
+    return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad, &ca);
+  }
   if (fuse) {
     PassArgs ad{};
     ad.th_upd = theta_micro;

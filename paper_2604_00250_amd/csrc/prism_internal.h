@@ -106,6 +106,12 @@ struct PassArgs {
   float* v_micro;
   const int32_t* step;
   float lr, b1, b2, eps;
+  // set by prism_iteration_adam when the step counter advances at the start of
+  // the call (k_fractions, block 0): the Adam updates then use t = step[0]
+  int32_t* step_advance;   // the counter to advance (nullptr: no advance here)
+  int32_t step_ready;      // 1: step[0] already counts this step
+  double* calsq;           // [n_groups][3] sums of squares of alpha, beta, bias (nullptr: not needed)
+  int32_t n_groups;
 };
 
 struct ReduceArgs {
@@ -123,6 +129,15 @@ struct ReduceArgs {
   ModelDev model;
   int32_t n_tiles;
   int32_t n_groups;
+  // calibration Adam applied where each gradient entry is written (fused
+  // iteration): theta_cal, moments and hyper-parameters; t = step[0]
+  int32_t cal_adam;
+  float* th_cal_upd;       // the same buffer as th_cal
+  float* m_cal;
+  float* v_cal;
+  const int32_t* step;
+  float lr, b1, b2, eps;
+  const double* calsq;     // precomputed [n_groups][3] (the cal prior's loss) or nullptr
 };
 
 struct StitchArgs {

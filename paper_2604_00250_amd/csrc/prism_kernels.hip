@@ -23,9 +23,39 @@ namespace prism {
 constexpr int kAuxBlock = 512;
 
 // fractions f = softmax(logits) once per voxel, rows [V][C] (CT: see load_row)
+// The first kernel of a call also does two small jobs of the fused iteration
+// before anything reads or changes the parameters: block 0 advances the step
+// counter, and blocks n_items.. (one per group) sum the squares of the group's
+// calibration parameters for the calibration prior's loss.
 template <int CT>
 __global__ __launch_bounds__(kAuxBlock) void k_fractions(PassArgs A) {
-  const ItemDev it = A.items[xcd_item(blockIdx.x, gridDim.x)];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && A.step_advance) {
+    A.step_advance[0] = A.step_advance[0] + 1;
+    A.step_advance[1] = 0;
+  }
+  if ((int)blockIdx.x >= A.n_items) {
+    // one wave, fixed order (the same bits whatever the launch's block size)
+    if (threadIdx.x >= 64) return;
+    const int gi = blockIdx.x - A.n_items;
+    const GroupDev g = A.groups[gi];
+    const float* cal = A.th_cal + g.cal_off;
+    double sa = 0.0, sb = 0.0, sw = 0.0;
+    for (int i = threadIdx.x; i < g.n_bias; i += 64) sw += (double)cal[i] * cal[i];
+    for (int i = threadIdx.x; i < g.N; i += 64) {
+      sa += (double)cal[g.n_bias + i] * cal[g.n_bias + i];
+      sb += (double)cal[g.n_bias + g.N + i] * cal[g.n_bias + g.N + i];
+    }
+    sa = wave_sum_f64(sa);
+    sb = wave_sum_f64(sb);
+    sw = wave_sum_f64(sw);
+    if (threadIdx.x == 0) {
+      A.calsq[3 * gi + 0] = sa;
+      A.calsq[3 * gi + 1] = sb;
+      A.calsq[3 * gi + 2] = sw;
+    }
+    return;
+  }
+  const ItemDev it = A.items[xcd_item(blockIdx.x, A.n_items)];
   const GroupDev g = A.groups[it.group];
   if (!((g.priors & kPriorSpatial) && g.nbh > 0)) return;
   const float* th = A.th_micro + g.micro_off;
@@ -263,8 +293,13 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
   float* gc = R.g_cal + g.cal_off;
   const int N = g.N, nb = g.n_bias;
   const bool cal_on = (g.priors & kPriorCal) != 0;
-  // calibration L2 (Sec. 2.4) on block 0 of the group
-  if (fc == 0) {
+  // read before any thread of this block updates the calibration vector in place
+  const float sigma_log = cal[nb + 2 * N];
+  __shared__ float adam_sc[2];
+  if (R.cal_adam && threadIdx.x == 0) adam_factors(R.step, R.lr, R.b1, R.b2, adam_sc[0], adam_sc[1], 1);
+  // calibration L2 (Sec. 2.4) on block 0 of the group (precomputed when the
+  // calibration vector is updated here)
+  if (fc == 0 && !R.calsq) {
     double sa = 0.0, sb = 0.0, sw = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) sw += (double)cal[i] * cal[i];
     for (int i = threadIdx.x; i < N; i += 256) {
@@ -315,14 +350,20 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
   if (write) {
     gc[dst] = out;
     if (!isfinite(out)) atomicOr(R.status, (uint32_t)kStNonfiniteGrad);
+    if (R.cal_adam) {
+      float p = R.th_cal_upd[g.cal_off + dst], m = R.m_cal[g.cal_off + dst], v = R.v_cal[g.cal_off + dst];
+      adam_one(p, out, m, v, R.b1, R.b2, R.eps, adam_sc[0], adam_sc[1]);
+      R.th_cal_upd[g.cal_off + dst] = p;
+      R.m_cal[g.cal_off + dst] = m;
+      R.v_cal[g.cal_off + dst] = v;
+    }
   }
   if (fc == 0 && f == 0) {
     // loss terms from fields 0-7 of the LDS partials of this (first) field chunk
     auto part_sum = [&](int fld) { return part[0][fld] + part[1][fld] + part[2][fld] + part[3][fld]; };
     const double data = g.mode == kMSE
                             ? part_sum(kRecData) * (double)g.invM
-                            : part_sum(kRecData) +
-                                  2.0 * (double)cal[nb + 2 * N] * (double)N * M;
+                            : part_sum(kRecData) + 2.0 * (double)sigma_log * (double)N * M;
     const double sp = part_sum(kRecSpatial) * (double)R.model.lam_sp * g.invM;
     const double rp = part_sum(kRecRep) * (double)R.model.lam_rep * g.invM;
     const double sa = part_sum(kRecSparse) * (double)R.model.lam_sparse * g.invM;
@@ -332,9 +373,10 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
     const double tv = part_sum(kRecTV) * (double)R.model.lam_tv * g.invM;
     double cl = 0.0;
     if (cal_on) {
-      const double qa = calsq[0][0] + calsq[0][1] + calsq[0][2] + calsq[0][3];
-      const double qb = calsq[1][0] + calsq[1][1] + calsq[1][2] + calsq[1][3];
-      const double qw = calsq[2][0] + calsq[2][1] + calsq[2][2] + calsq[2][3];
+      const double* pre = R.calsq ? R.calsq + 3 * gi : nullptr;
+      const double qa = pre ? pre[0] : calsq[0][0] + calsq[0][1] + calsq[0][2] + calsq[0][3];
+      const double qb = pre ? pre[1] : calsq[1][0] + calsq[1][1] + calsq[1][2] + calsq[1][3];
+      const double qw = pre ? pre[2] : calsq[2][0] + calsq[2][1] + calsq[2][2] + calsq[2][3];
       cl = (double)R.model.lam_alpha * qa + (double)R.model.lam_beta * qb +
            (double)R.model.lam_bias * qw;
     }
@@ -406,6 +448,16 @@ __global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* t
     const float out = (float)(s + (cal_on ? 2.0 * (double)R.model.lam_bias * cal[cp] : 0.0));
     R.g_cal[g.cal_off + cp] = out;
     if (!isfinite(out)) atomicOr(R.status, (uint32_t)kStNonfiniteGrad);
+    if (R.cal_adam) {
+      float ss, ib;
+      adam_factors(R.step, R.lr, R.b1, R.b2, ss, ib, 1);
+      const int64_t i = g.cal_off + cp;
+      float p = R.th_cal_upd[i], m = R.m_cal[i], v = R.v_cal[i];
+      adam_one(p, out, m, v, R.b1, R.b2, R.eps, ss, ib);
+      R.th_cal_upd[i] = p;
+      R.m_cal[i] = m;
+      R.v_cal[i] = v;
+    }
   }
 }
 
@@ -506,7 +558,8 @@ hipError_t launch_pass_maxn(const PassArgs& a, int K, int mode, int learn_d, int
 
 template <int CT>
 static void launch_spatial_t(const PassArgs& a, dim3 grid, dim3 block, hipStream_t s) {
-  hipLaunchKernelGGL(k_fractions<CT>, grid, block, 0, s, a);
+  const dim3 fgrid(grid.x + (a.calsq ? a.n_groups : 0));
+  hipLaunchKernelGGL(k_fractions<CT>, fgrid, block, 0, s, a);
   hipLaunchKernelGGL(k_spatial<CT>, grid, block, 0, s, a);
 }
 

@@ -455,7 +455,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   const float4* acq_tab = acq;
 #endif
   for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
-  if (A.adam && tid == 0) adam_factors(A.step, A.lr, A.b1, A.b2, sh.adam_sc[0], sh.adam_sc[1]);
+  if (A.adam && tid == 0) adam_factors(A.step, A.lr, A.b1, A.b2, sh.adam_sc[0], sh.adam_sc[1], A.step_ready);
   __syncthreads();
 
   const int nb = (N * split) / WN, ne = (N * (split + 1)) / WN;

@@ -181,6 +181,8 @@ def autotune(state, reps: int = 5, cache: Optional[str] = DEFAULT_CACHE, cands: 
                     kb = bucket_key(b)
                     best_shape, best_b_ms = None, cur_ms
                     for shape in bucket_candidates(persistent):
+                        if shape == base[kb]:
+                            continue  # the problem-wide shape itself: already timed as cur_ms
                         trial = [c for c in chosen if bucket_key(c) != kb] + [dict(b, **shape)]
                         try:
                             _apply(state, best, trial)
