@@ -62,6 +62,14 @@ ALG_VALU_PER_PAIR = 84
 #   total 19K + 15 = 72 VALU and 2K = 6 exps; reported as frac_min_count.
 MIN_VALU_PER_PAIR = 72
 ALG_EXP_PER_PAIR = 6
+# At b = 0 every attenuation is exactly 1 and the kernel runs whole 16-measurement
+# tiles of an acquisition's leading b = 0 measurements with the data term and the
+# calibration adjoints only: yhat - beta, yhat, residual, squared-residual
+# accumulate, seed x (yhat - beta) and its accumulate, the compartments' adjoint
+# accumulate -> 7 VALU, no exp.  The frozen count above prices every pair alike;
+# frac_b0_aware prices these pairs at this count instead.
+B0_VALU_PER_PAIR = 7
+B0_TILE = 16
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam
 # moments read (8P) + theta and moments written (12P)
@@ -292,6 +300,77 @@ def parse_launch(text):
     return dict(zip(keys, vals))
 
 
+def _oracle_fit(g, iterations, lr, budget_s):
+    """The oracle's own fit (its loss_grad and Adam in FP64, one process, one
+    thread) from the workload's initial parameters, for at most `budget_s`
+    seconds; returns (iterations done, seconds, loss after the last one)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    prob = O.Problem(coords=g.coords, shape=tuple(g.shape), bval=np.asarray(g.acq.bval, np.float64),
+                     bvec=np.asarray(g.acq.bvec, np.float64), K=g.K, mode=g.mode, bias=g.bias,
+                     learn_diffusivity=g.learn_diffusivity, neighbourhood=g.neighbourhood,
+                     priors=tuple(g.priors))
+    th = {k: np.asarray(np.asarray(v, np.float32), np.float64) for k, v in g.theta.items()}
+    m = {k: np.zeros_like(v) for k, v in th.items()}
+    v2 = {k: np.zeros_like(v) for k, v in th.items()}
+    y = np.asarray(g.y, np.float64)
+    t0 = time.perf_counter()
+    done, loss = 0, None
+    with threadpool_limits(1):
+        while done < iterations and (done == 0 or time.perf_counter() - t0 < budget_s):
+            out, grad, _ = O.loss_grad(prob, th, y)
+            loss = out["total"]
+            for k in th:
+                th[k], m[k], v2[k] = O.adam_step(th[k], grad[k], m[k], v2[k], done + 1, lr=lr)
+            done += 1
+    return done, time.perf_counter() - t0, loss
+
+
+def bench_patches(args):
+    """Whole fits of the two single-patch workloads on the GPU (the iteration
+    captured as a HIP graph and replayed), beside the oracle's own fit on one
+    host core: one 8^3 patch (N = 33, K = 3, MSE, 100 Adam steps) and one 16^3
+    patch (N = 288, K = 3, Rician NLL with calibration, 500 iterations; the
+    oracle runs a bounded number of its iterations and the rate is scaled)."""
+    import torch
+    from paper_2604_00250_amd import _lib as L
+    from paper_2604_00250_amd import inputs as I
+    from paper_2604_00250_amd.fit import fit
+    from paper_2604_00250_amd.problem import DeviceState, Problem
+    res = []
+    for w, budget in ((I.patch8_crossings(priors=I.PRIOR_NAMES), 30.0), (I.patch16_hcp(), 20.0)):
+        g = w.groups[0]
+        prob = Problem([g])
+        st = DeviceState(prob, ys=[g.y], thetas=[g.theta], device="cuda:0")
+        fit(st, 20, lr=w.lr)                          # warm-up fit (captures, replays, restores nothing)
+        st.set_params([g.theta])
+        st.reset_optimizer()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        hist = fit(st, w.iterations, lr=w.lr)
+        wall = time.perf_counter() - t
+        h = hist[:, 0].cpu().numpy()
+        n_done, cpu_s, cpu_loss = _oracle_fit(g, w.iterations, w.lr, budget)
+        res.append(dict(workload=w.name, voxels=g.n_vox, measurements=g.acq.n, iterations=w.iterations,
+                        gpu_fit_s=wall, gpu_ms_per_iteration=wall / w.iterations * 1e3,
+                        gpu_voxel_iters_per_s=g.n_vox * w.iterations / wall,
+                        loss_first=float(h[0, L.LOSS_TOTAL]), loss_last=float(h[-1, L.LOSS_TOTAL]),
+                        status=int(st.status.item()),
+                        oracle_iterations_timed=n_done, oracle_s=cpu_s,
+                        oracle_fit_s=cpu_s / n_done * w.iterations,
+                        oracle_fit_s_note="measured" if n_done == w.iterations else
+                        f"scaled from {n_done} of {w.iterations} iterations",
+                        oracle_voxel_iters_per_s=g.n_vox * n_done / cpu_s,
+                        oracle_loss_at_last_timed_iteration=float(cpu_loss),
+                        gpu_loss_at_same_iteration=float(h[n_done - 1, L.LOSS_TOTAL])))
+        log(f"{w.name}: GPU {wall * 1e3:.1f} ms for {w.iterations} iterations; oracle {cpu_s:.1f} s for {n_done}")
+        del st
+    out = {"metric": METRIC, "value": None, "unit": "s per fit", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f32", "config": {"workload": "patch fits"}, "fits": res}
+    print(json.dumps(out), flush=True)
+
+
 def tuned_report(tuned):
     """The autotuner's choices: the problem-wide shape with its time and the
     runners-up, then each bucket's shape (an override where one beat the
@@ -454,9 +533,10 @@ def main():
                     help="skip the prism_loss_grad-only leg (counter runs see the timed kernel only)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--launch", type=str, default="", help="vox_per_lane,n_split,item_vox[,persistent]")
-    ap.add_argument("--workload", choices=("brain", "batched"), default="brain",
+    ap.add_argument("--workload", choices=("brain", "batched", "patches"), default="brain",
                     help="brain: the 743k-voxel volume (the metric's configuration); batched: 4096 "
-                         "independent uneven patches in one problem, autotuned launch")
+                         "independent uneven patches in one problem, autotuned launch; patches: whole "
+                         "fits of the 8^3 and 16^3 patch workloads beside the oracle's")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures the single-GPU path only: the fused pass runs on one MI355X "
@@ -469,6 +549,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "patches":
+        return bench_patches(args)
     t0 = time.time()
     w = I.brain_volume()
     g = w.groups[0]
@@ -544,6 +626,12 @@ def main():
     q = mb["q_exp"] if mb else 1.0
     slots = pairs * (ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR)
     achieved = slots / (k_ms * 1e-3)
+    nb0 = 0
+    while nb0 < g.acq.n and g.acq.bval[nb0] == 0.0:
+        nb0 += 1
+    b0_short = (nb0 // B0_TILE) * B0_TILE if prob.launch()["n_split"] == 1 else 0
+    slots_b0 = V * (b0_short * B0_VALU_PER_PAIR
+                    + (g.acq.n - b0_short) * (ALG_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR))
     traffic = stored_traffic(w.name)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_SLOTS / 1e12, unit="Tslot/s",
                     frac=achieved / PEAK_SLOTS, traffic=traffic,
@@ -553,6 +641,8 @@ def main():
                     frac_min_count=pairs * (MIN_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR) / (k_ms * 1e-3)
                     / PEAK_SLOTS,
                     min_slots_per_pair=MIN_VALU_PER_PAIR + q * ALG_EXP_PER_PAIR,
+                    frac_b0_aware=slots_b0 / (k_ms * 1e-3) / PEAK_SLOTS,
+                    b0_pairs_per_voxel_short=b0_short,
                     hbm_GBps=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / 1e9,
                     hbm_frac=ALG_BYTES_PER_VOXEL * V / (k_ms * 1e-3) / PEAK_HBM)
     out = {

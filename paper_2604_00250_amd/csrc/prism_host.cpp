@@ -489,6 +489,8 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
       }
     }
     g.acq_off = acq_off[d.acq];
+    g.nb0 = 0;
+    while (g.nb0 < g.N && bval[(size_t)g.acq_off + g.nb0] == 0.0f) ++g.nb0;
     g.rec_stride = kRecHead + 2 * g.N;
     g.invM = V > 0 ? 1.0f / (float)V : 0.0f;
     g.ntab = ntab;

@@ -50,6 +50,7 @@ struct GroupDev {
   float bsc[3], boff[3]; // quadratic bias coordinates xi_a = i_a bsc[a] + boff[a] in [-1, 1]
                          // (2/(n_a - 1) and -1; both 0 when n_a = 1)
   int32_t acq_off;    // offset of the group's measurements in the acquisition arrays
+  int32_t nb0;        // measurements with b = 0 at the start of the acquisition
   int32_t rec_stride; // float64 fields per record
   int32_t item_begin, item_count;
   int32_t tile_begin, tile_count;  // first-stage reduction tiles of this group

@@ -217,6 +217,47 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
 // ---------------------------------------------------------------------------
 // one (voxel, measurement) pair: forward, data term, adjoint accumulation
 // ---------------------------------------------------------------------------
+// Data term of one pair (Eq. 8 / Eq. 9) and its seed dL/dyhat (MSE: without
+// the 2/|M| applied per voxel later).  valid (0 for lanes past the end of the
+// item) zeroes the lane's residual, so the loss, the per-measurement sums and
+// the (unstored) adjoint all drop it.
+template <int MODE>
+__device__ __forceinline__ void data_term(float yh, float yv, float valid, float inv_s2, float& t_loss,
+                                          float& t_sig, float& seed) {
+  if (MODE == kMSE) {
+    const float r = (yh - yv) * valid;
+    seed = r;
+    t_loss = r * r;
+    t_sig = 0.0f;
+  } else {
+    const float ay = fabsf(yv), ah = fabsf(yh);
+    const float z = ay * ah * inv_s2;
+    float omr, qz;
+    const float li = log_i0e(z, omr, qz);
+    const float dd = ah - ay;
+    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li) * valid;
+    t_sig = fmaf(dd * dd, inv_s2, qz) * valid;  // qz = 2z (1 - R(z))
+    const float sd = fmaf(ay, omr, dd) * inv_s2 * valid;
+    seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
+  }
+}
+
+// One pair at b = 0: every attenuation of Eq. 4-5 is exactly 1, so S = sum_c F_c
+// (Fsum) and the fibre-angle, f_intra and diffusivity adjoints vanish; the
+// compartments' adjoint, dS for each of them, is summed once (dS0) and added to
+// every compartment after the b = 0 measurements.
+template <int MODE>
+__device__ __forceinline__ void pair_b0(float Fsum, float& logb_acc, float& dS0, float yv, float valid,
+                                        const float4 c, float inv_s2, float& t_loss, float& t_sig,
+                                        float& sq, float& seed) {
+  const float q = c.x * Fsum;
+  const float yh = q + c.y;
+  data_term<MODE>(yh, yv, valid, inv_s2, t_loss, t_sig, seed);
+  sq = seed * q;
+  logb_acc += sq;
+  dS0 = fmaf(seed, c.x, dS0);
+}
+
 template <int K, int MODE, bool LD>
 __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv, float valid,
                                      const float4 a, const float4 b, const float4 c, float inv_s2,
@@ -240,24 +281,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   }
   const float q = c.x * S;                // yhat - beta (B is in F)
   const float yh = q + c.y;               // Eq. 6
-  // valid (0 for lanes past the end of the item) zeroes the lane's residual, so
-  // the loss, the per-measurement sums and the (unstored) adjoint all drop it
-  if (MODE == kMSE) {
-    const float r = (yh - yv) * valid;
-    seed = r;
-    t_loss = r * r;
-    t_sig = 0.0f;
-  } else {
-    const float ay = fabsf(yv), ah = fabsf(yh);
-    const float z = ay * ah * inv_s2;
-    float omr, qz;
-    const float li = log_i0e(z, omr, qz);
-    const float dd = ah - ay;
-    t_loss = fmaf(dd * dd, 0.5f * inv_s2, -li) * valid;
-    t_sig = fmaf(dd * dd, inv_s2, qz) * valid;  // qz = 2z (1 - R(z))
-    const float sd = fmaf(ay, omr, dd) * inv_s2 * valid;
-    seed = yh < 0.0f ? -sd : sd;          // sgn(yhat) [(|yhat|-|y|) + |y|(1-R)] / s^2
-  }
+  data_term<MODE>(yh, yv, valid, inv_s2, t_loss, t_sig, seed);
   sq = seed * q;
   acc.r[Acc<K, LD>::kLogB] += sq;
   // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of fibre c's signal
@@ -309,7 +333,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
                                                  const float* yg, int64_t V, const int (&vox)[VL],
                                                  const float (&valid)[VL],
                                                  const float4* __restrict__ acq,
-                                                 int nb, int ne, int N, float inv_s2, int lane,
+                                                 int nb, int ne, int nb0, int N, float inv_s2, int lane,
                                                  float* wacc, double& dloss, double& dsig) {
   const int lane16 = lane & 15;
   uint32_t voff[VL];  // byte offsets of the lane's voxels in a row of y
@@ -359,6 +383,29 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     sacc = 0.0f;
     sel = lane16 == 0 ? 1.0f : 0.0f;
   };
+  // the same at b = 0 (see pair_b0)
+  float Fsum[VL], dS0[VL];
+  auto body_b0 = [&](int t, float (&slot)[VL]) {
+    const int n = n0 + t;
+    const float4 c = acq[3 * n + 2];
+    float pa = 0.0f, pb = 0.0f;
+#pragma unroll
+    for (int j = 0; j < VL; ++j) {
+      float tl, ts, sq, sd;
+      pair_b0<MODE>(Fsum[j], acc[j].r[Acc<K, LD>::kLogB], dS0[j], slot[j], FULL ? 1.0f : valid[j], c, inv_s2,
+                    tl, ts, sq, sd);
+      lacc += tl;
+      if (MODE == kNLL) sacc += ts;
+      pa = j == 0 ? sq : pa + sq;
+      pb = j == 0 ? sd : pb + sd;
+    }
+    const float* row = yg + (int64_t)min(n + kPf, ne - 1) * V;  // clamped: in bounds
+#pragma unroll
+    for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
+    Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
+    Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
+    sel = dpp_f32<0x111>(sel);
+  };
   // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
   auto group = [&](int t0) {
 #pragma unroll
@@ -383,6 +430,32 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     dloss += (double)lacc;
     dsig += (double)sacc;
   };
+  // whole tiles of the acquisition's leading b = 0 measurements first
+  const int b0end = min(nb0, ne);
+  if (n0 + kTile <= b0end) {
+#pragma unroll
+    for (int j = 0; j < VL; ++j) {
+      float sF = 0.0f;
+#pragma unroll
+      for (int cc = 0; cc < K + 3; ++cc) sF += x[j].F[cc];
+      Fsum[j] = sF;
+      dS0[j] = 0.0f;
+    }
+    for (; n0 + kTile <= b0end; n0 += kTile) {
+      tile_begin();
+#pragma unroll 1
+      for (int t0 = 0; t0 < kTile; t0 += kPf) {
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) body_b0(t0 + u, yr[u]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      tile_end(kTile);
+    }
+#pragma unroll
+    for (int j = 0; j < VL; ++j)
+#pragma unroll
+      for (int cc = 0; cc < K + 3; ++cc) acc[j].r[cc] += dS0[j];
+  }
   if (MODE == kMSE) {
     // whole tiles: every path into the loop has the ring's loads in flight in slot
     // order, so each wait is for exactly one slot
@@ -501,10 +574,10 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
     // a chunk that lies wholly inside the item runs the loop without validity factors
     if (cb + chunk <= it.nv)
-      measurement_loop<K, MODE, LD, VL, true>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
+      measurement_loop<K, MODE, LD, VL, true>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, g.nb0, N, inv_s2, lane,
                                               wacc, dloss, dsig);
     else
-      measurement_loop<K, MODE, LD, VL, false>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, N, inv_s2, lane,
+      measurement_loop<K, MODE, LD, VL, false>(x, acc, yg, V, vox, valid, acq_tab, nb, ne, g.nb0, N, inv_s2, lane,
                                                wacc, dloss, dsig);
 
     // combine the per-voxel accumulators of the waves that split this row over n
