@@ -51,24 +51,27 @@ ALG_VALU_PER_PAIR = 84
 # The fewest operations the implementation's algebra needs for the same pair
 # (every operation of Eq. 3-6, the data term and the adjoint counted once, an
 # FMA as one, fused wherever the algebra allows, per-voxel factors such as the
-# bias field and each fibre's fraction applied once per voxel):
-#   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2,
-#     f_intra mix 1, product 1, accumulate 1 (9K); gain and offset 2 -> 9K + 5
-#   data term: residual 1, squared-residual accumulate 1                  -> 2
-#   adjoint: seed*q 1 and its accumulate 1, dS 1, dS(-2b) 1, isotropic 3,
-#     f_intra accumulate 1; per fibre fraction 1, e1(1-e2) 1 (one FMA),
-#     f_intra sum 1, bracket 1, cos e1 1, *bracket 1, *dS(-2b) 1,
-#     direction 3 (10K)                                               -> 10K + 8
-#   total 19K + 15 = 72 VALU and 2K = 6 exps; reported as frac_min_count.
-MIN_VALU_PER_PAIR = 72
+# bias field, each fibre's fraction and f_intra applied once per voxel; a fibre's
+# attenuation taken as f_in e1 + (1 - f_in) e12 with e1 and e12 = e1 e2 one exp
+# each, so that e2 is never formed and the f_intra and log-bias adjoints follow
+# per voxel from the per-fibre sums of dS e1 and dS e12):
+#   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2, two
+#     weighted adds into S 2 (8K)                                     -> 8K + 3
+#   data term: beta - y 1, residual (gain S + (beta - y)) 1, squared-residual
+#     accumulate 1                                                      -> 3
+#   adjoint: seed S 1 (the alpha_n sum's input), dS 1, dS(-2b) 1, isotropic 3;
+#     per fibre the sums of dS e1 and dS e12 2, a2 e12 1, a1 e1 + a2 e12 1,
+#     cos dS(-2b) 1, times that 1, direction 3 (9K)                     -> 9K + 6
+#   total 17K + 12 = 63 VALU and 2K = 6 exps; reported as frac_min_count.
+MIN_VALU_PER_PAIR = 63
 ALG_EXP_PER_PAIR = 6
 # At b = 0 every attenuation is exactly 1 and the kernel runs whole 16-measurement
 # tiles of an acquisition's leading b = 0 measurements with the data term and the
-# calibration adjoints only: yhat - beta, yhat, residual, squared-residual
-# accumulate, seed x (yhat - beta) and its accumulate, the compartments' adjoint
-# accumulate -> 7 VALU, no exp.  The frozen count above prices every pair alike;
-# frac_b0_aware prices these pairs at this count instead.
-B0_VALU_PER_PAIR = 7
+# calibration adjoints only: beta - y, residual, squared-residual accumulate,
+# seed x S (the alpha_n sum's input), the compartments' adjoint accumulate -> 5
+# VALU, no exp.  The frozen count above prices every pair alike; frac_b0_aware
+# prices these pairs at this count instead.
+B0_VALU_PER_PAIR = 5
 B0_TILE = 16
 # Algorithmic HBM bytes of one voxel of the fused pass as the timed iteration runs
 # it (prism_iteration_adam: Adam inside the pass): y (4N) + theta read (4P) + Adam

@@ -70,6 +70,13 @@ __device__ __forceinline__ float dpp_f32(float x) {
                                          false));
 }
 
+// row_shr:1 within each row of 16 lanes, the row's first lane reading 0 (bound
+// control set: no separate "old" operand has to be written first)
+__device__ __forceinline__ float row_shr1_zero(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x111, 0xf, 0xf, true));
+}
+
 // Sum over the 64 lanes of a wave; the total lands in lane 63 (other lanes hold
 // partial sums).  quad_perm xor 1, xor 2, half-row mirror, row mirror, then
 // the two row broadcasts that chain rows 0-3.

@@ -22,6 +22,9 @@ namespace prism {
 #ifndef PRISM_PREFETCH
 #define PRISM_PREFETCH 4
 #endif
+#ifndef PRISM_FOUR_WAVES
+#define PRISM_FOUR_WAVES 1
+#endif
 // measurements per matrix-core reduction tile (8 or 16 columns of the 16x16 tile)
 constexpr int kTile = PRISM_TILE;
 // depth of the y prefetch ring (measurements ahead); kTile is a multiple of it
@@ -29,21 +32,32 @@ constexpr int kPf = PRISM_PREFETCH;
 static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
 
 
-// Waves per SIMD that the register allocation of the fused pass must allow:
-// three for the variants that fit 168 registers without spilling (one voxel
-// per lane, at most two fibres, or three with fixed diffusivities), else
-// PRISM_PASS_MIN_WAVES.  Those variants also let the scheduler interleave two
-// measurements at a time (sched_span 2), which the limit keeps within 168.
-constexpr int pass_min_waves(int K, bool LD, int VL) {
-  return VL == 1 && (K <= 2 || (K == 3 && !LD)) ? 3 : PRISM_PASS_MIN_WAVES;
+// Waves per SIMD that the register allocation of the fused pass must allow.
+// MSE with fixed diffusivities and at most three fibres, one voxel per lane:
+// four (128 registers; the measurement loop stays free of spills, the few
+// spills are in the per-voxel prologue and epilogue), scheduling one
+// measurement at a time.  Otherwise three for the variants that fit 168
+// registers without spilling (one voxel per lane, at most two fibres, or three
+// with fixed diffusivities), letting the scheduler interleave two measurements
+// at a time (sched_span 2); else PRISM_PASS_MIN_WAVES, one measurement at a time.
+constexpr bool pass_four_waves(int K, int MODE, bool LD, int VL) {
+  return PRISM_FOUR_WAVES && VL == 1 && MODE == 0 && !LD && K <= 3;
 }
-constexpr int sched_span(int K, bool LD, int VL) { return pass_min_waves(K, LD, VL) == 3 ? 2 : 1; }
+constexpr int pass_min_waves(int K, int MODE, bool LD, int VL) {
+  return pass_four_waves(K, MODE, LD, VL) ? 4
+         : VL == 1 && (K <= 2 || (K == 3 && !LD)) ? 3 : PRISM_PASS_MIN_WAVES;
+}
+constexpr int sched_span(int K, int MODE, bool LD, int VL) {
+  return pass_min_waves(K, MODE, LD, VL) == 3 ? 2 : 1;
+}
 
 // ---------------------------------------------------------------------------
 // staging of one measurement: 3 x float4
 //   a = (gx, gy, gz, kpar)   kpar  = -b Dpar log2(e)   (Dpar = 1 with learned D)
 //   b = (kperp, Ecsf, Egm, Eres)                          Eq. 4
-//   c = (exp(alpha_n), beta_n, -2 b, 0)                   adjoint factor
+//   c = (exp(alpha_n), beta_n, -2 b, kpar - kperp)        gain, offset, adjoint factor,
+//                                                         and the cos^2 coefficient of
+//                                                         log2(e1 e2) (0 with learned D)
 // ---------------------------------------------------------------------------
 inline __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* acq) {
   const float* cal = A.th_cal + g.cal_off;
@@ -57,40 +71,55 @@ inline __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, f
     acq[3 * n + 0] = make_float4(gv[0], gv[1], gv[2], -b * dpar * kLog2e);
     acq[3 * n + 1] = make_float4(-b * dperp * kLog2e, expf(-b * A.model.d_csf),
                                  expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
-    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b, 0.0f);
+    const float kpar = -b * dpar * kLog2e, kperp = -b * dperp * kLog2e;
+    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b, g.learn_d ? 0.0f : kpar - kperp);
   }
 }
 
 // ---------------------------------------------------------------------------
 // per-voxel state
 // ---------------------------------------------------------------------------
+// A fibre's attenuation (Eq. 5) is E_k = f_in e1 + (1 - f_in) e12 with
+// e1 = exp(-b Dpar cos^2) and e12 = e1 e2 = exp(-b Dpar cos^2 - b Dperp sin^2):
+// both are taken as one exp each, so e2 itself is never formed, and every
+// per-voxel factor (B S0 f_k f_in, B S0 f_k (1 - f_in)) multiplies them directly.
 template <int K, bool LD>
 struct Vox {
-  float F[K + 3];   // B S0 * fraction (bias field folded in), order csf, gm, wm_0..wm_{K-1}, res
+  float Fi[3];      // B S0 * fraction of csf, gm, res (bias field folded in)
+  float Fa[K];      // B S0 f_k f_in:       weight of e1
+  float Fb[K];      // B S0 f_k (1 - f_in): weight of e12
   float d[K][3];    // unit directions
-  float fin, omf;   // f_intra, 1 - f_intra
-  float dpq, dqfin; // Dpar - Dperp, Dperp f_intra (the fibre-angle adjoint)
+  float a1, a2;     // Dpar f_in, (Dpar - Dperp)(1 - f_in): dE/dcos = -2b cos (a1 e1 + a2 e12)
   float dpar, dperp;
 };
 
-// per-voxel adjoint accumulators as one register array (constant indices only)
+// per-voxel adjoint accumulators as one register array (constant indices only);
+// with dS = seed exp(alpha_n) the sums over the measurements are
+//   r[0..2]        sum dS E_c  of csf, gm, res
+//   r[kE1 + k]     sum dS e1_k,  r[kE12 + k] sum dS e12_k
+//                  (fibre k's sum dS E_k = f_in r[kE1+k] + (1 - f_in) r[kE12+k] and
+//                  its f_in derivative sum dS (e1 - e12) come from these per voxel)
+//   r[kGd + 3k..]  sum dcos_k g_n, the direction adjoint divided by F_k
+// and the log-bias adjoint sum seed (yhat - beta) = sum_c F_c sum dS E_c is
+// formed from them per voxel.
 template <int K, bool LD>
 struct Acc {
-  static constexpr int C = K + 3;
-  static constexpr int kGd = C;               // sum_n dc_k g_n / F_k (dL/dd_k / F_k), 3K
-  static constexpr int kFin = C + 3 * K;      // sum_n sum_k dE_k e1 (1 - e2)
-  static constexpr int kLogB = C + 3 * K + 1; // sum_n seed (yhat - beta)
-  static constexpr int kDpar = C + 3 * K + 2; // learned diffusivities
-  static constexpr int kDperp = C + 3 * K + 3;
-  static constexpr int N = C + 3 * K + 2 + (LD ? 2 : 0);
-  float r[N];                                 // r[c] = sum_n dS E_c (dL/dF_c / B)
+  static constexpr int kE1 = 3;
+  static constexpr int kE12 = 3 + K;
+  static constexpr int kGd = 3 + 2 * K;
+  static constexpr int kDpar = 3 + 5 * K;     // learned diffusivities
+  static constexpr int kDperp = 4 + 5 * K;
+  static constexpr int N = 3 + 5 * K + (LD ? 2 : 0);
+  float r[N];
 };
+constexpr int acc_count(int K, bool LD) { return 3 + 5 * K + (LD ? 2 : 0); }
 
 
 struct Derived {            // quantities the epilogue needs again
   float S0, sig_s;
   float f[kMaxC];
   float invn[kMaxK];
+  float fin, omf;           // f_intra, 1 - f_intra
   float sig_dpar, sig_dperp;
   float B;                  // bias field
 };
@@ -173,10 +202,7 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
   dv.B = exp_hw(log_bias(g, cal, A.coords[g.vox_off + v]));
   const float BS0 = dv.B * dv.S0;
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    dv.f[c] = lg[c] * inv;
-    x.F[c] = BS0 * dv.f[c];
-  }
+  for (int c = 0; c < C; ++c) dv.f[c] = lg[c] * inv;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float vx = th[(int64_t)row_v(C, k, 0) * V + v];
@@ -194,8 +220,19 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     x.d[k][1] = vy * in;
     x.d[k][2] = vz * in;
   }
-  x.fin = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
-  x.omf = 1.0f - x.fin;
+  const float fin = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
+  const float omf = 1.0f - fin;
+  dv.fin = fin;
+  dv.omf = omf;
+  x.Fi[0] = BS0 * dv.f[0];
+  x.Fi[1] = BS0 * dv.f[1];
+  x.Fi[2] = BS0 * dv.f[C - 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float F = BS0 * dv.f[2 + k];
+    x.Fa[k] = F * fin;
+    x.Fb[k] = F * omf;
+  }
   if (LD) {
     const float a = th[(int64_t)row_dpar(C, K) * V + v];
     const float b = th[(int64_t)(row_dpar(C, K) + 1) * V + v];
@@ -209,27 +246,29 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     dv.sig_dpar = 0.0f;
     dv.sig_dperp = 0.0f;
   }
+  const float dpar = LD ? x.dpar : A.model.d_par;
   const float dperp = LD ? x.dperp : A.model.d_perp;
-  x.dpq = (LD ? x.dpar : A.model.d_par) - dperp;
-  x.dqfin = dperp * x.fin;
+  x.a1 = dpar * fin;
+  x.a2 = (dpar - dperp) * omf;
 }
 
 // ---------------------------------------------------------------------------
 // one (voxel, measurement) pair: forward, data term, adjoint accumulation
 // ---------------------------------------------------------------------------
-// Data term of one pair (Eq. 8 / Eq. 9) and its seed dL/dyhat (MSE: without
-// the 2/|M| applied per voxel later).  valid (0 for lanes past the end of the
-// item) zeroes the lane's residual, so the loss, the per-measurement sums and
-// the (unstored) adjoint all drop it.
+// Data term of one pair (Eq. 8 / Eq. 9) at yhat = gain S + beta (Eq. 6) and its
+// seed dL/dyhat (MSE: without the 2/|M| applied per voxel later).  valid (0 for
+// lanes past the end of the item) zeroes the lane's residual, so the loss, the
+// per-measurement sums and the (unstored) adjoint all drop it.
 template <int MODE>
-__device__ __forceinline__ void data_term(float yh, float yv, float valid, float inv_s2, float& t_loss,
-                                          float& t_sig, float& seed) {
+__device__ __forceinline__ void data_term(float S, float gain, float beta, float yv, float valid,
+                                          float inv_s2, float& t_loss, float& t_sig, float& seed) {
   if (MODE == kMSE) {
-    const float r = (yh - yv) * valid;
+    const float r = fmaf(gain, S, beta - yv) * valid;
     seed = r;
     t_loss = r * r;
     t_sig = 0.0f;
   } else {
+    const float yh = fmaf(gain, S, beta);
     const float ay = fabsf(yv), ah = fabsf(yh);
     const float z = ay * ah * inv_s2;
     float omr, qz;
@@ -245,16 +284,13 @@ __device__ __forceinline__ void data_term(float yh, float yv, float valid, float
 // One pair at b = 0: every attenuation of Eq. 4-5 is exactly 1, so S = sum_c F_c
 // (Fsum) and the fibre-angle, f_intra and diffusivity adjoints vanish; the
 // compartments' adjoint, dS for each of them, is summed once (dS0) and added to
-// every compartment after the b = 0 measurements.
+// every compartment after the b = 0 measurements.  sq = seed S: the
+// per-measurement sum of sq times exp(alpha_n) is the alpha_n adjoint.
 template <int MODE>
-__device__ __forceinline__ void pair_b0(float Fsum, float& logb_acc, float& dS0, float yv, float valid,
-                                        const float4 c, float inv_s2, float& t_loss, float& t_sig,
-                                        float& sq, float& seed) {
-  const float q = c.x * Fsum;
-  const float yh = q + c.y;
-  data_term<MODE>(yh, yv, valid, inv_s2, t_loss, t_sig, seed);
-  sq = seed * q;
-  logb_acc += sq;
+__device__ __forceinline__ void pair_b0(float Fsum, float& dS0, float yv, float valid, const float4 c,
+                                        float inv_s2, float& t_loss, float& t_sig, float& sq, float& seed) {
+  data_term<MODE>(Fsum, c.x, c.y, yv, valid, inv_s2, t_loss, t_sig, seed);
+  sq = seed * Fsum;
   dS0 = fmaf(seed, c.x, dS0);
 }
 
@@ -262,65 +298,60 @@ template <int K, int MODE, bool LD>
 __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float yv, float valid,
                                      const float4 a, const float4 b, const float4 c, float inv_s2,
                                      float& t_loss, float& t_sig, float& sq, float& seed) {
+  using AC = Acc<K, LD>;
   const float gx = a.x, gy = a.y, gz = a.z;
-  float S = x.F[0] * b.y;
-  S = fmaf(x.F[1], b.z, S);
-  S = fmaf(x.F[K + 2], b.w, S);
-  float cc[K], e1[K], e2[K], h[K], E[K];
+  const float kp = LD ? a.w * x.dpar : a.w;     // log2 e1 = kp cos^2
+  const float kq = LD ? b.x * x.dperp : b.x;    // log2 e12 = kq + (kp - kq) cos^2
+  const float kd = LD ? kp - kq : c.w;
+  float S = x.Fi[0] * b.y;
+  S = fmaf(x.Fi[1], b.z, S);
+  S = fmaf(x.Fi[2], b.w, S);
+  float cc[K], e1[K], e12[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     cc[k] = fmaf(gz, x.d[k][2], fmaf(gy, x.d[k][1], gx * x.d[k][0]));
     const float c2 = cc[k] * cc[k];
-    const float kp = LD ? a.w * x.dpar : a.w;
-    const float kq = LD ? b.x * x.dperp : b.x;
     e1[k] = ex2(kp * c2);                 // exp(-b Dpar cos^2)
-    e2[k] = ex2(fmaf(-kq, c2, kq));       // exp(-b Dperp sin^2)
-    h[k] = fmaf(x.omf, e2[k], x.fin);     // f_intra + (1 - f_intra) e2
-    E[k] = e1[k] * h[k];                  // Eq. 5
-    S = fmaf(x.F[2 + k], E[k], S);        // Eq. 3
+    e12[k] = ex2(fmaf(kd, c2, kq));       // exp(-b Dpar cos^2 - b Dperp sin^2)
+    S = fmaf(x.Fa[k], e1[k], S);          // Eq. 3 with Eq. 5: F_k (f_in e1 + (1 - f_in) e12)
+    S = fmaf(x.Fb[k], e12[k], S);
   }
-  const float q = c.x * S;                // yhat - beta (B is in F)
-  const float yh = q + c.y;               // Eq. 6
-  data_term<MODE>(yh, yv, valid, inv_s2, t_loss, t_sig, seed);
-  sq = seed * q;
-  acc.r[Acc<K, LD>::kLogB] += sq;
-  // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of fibre c's signal
+  data_term<MODE>(S, c.x, c.y, yv, valid, inv_s2, t_loss, t_sig, seed);
+  sq = seed * S;
+  // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of compartment c's signal
   const float dS = seed * c.x;
   const float dSz = dS * c.z;             // dS (-2b), the factor of dE/dcos shared by the fibres
   acc.r[0] = fmaf(dS, b.y, acc.r[0]);
   acc.r[1] = fmaf(dS, b.z, acc.r[1]);
-  acc.r[K + 2] = fmaf(dS, b.w, acc.r[K + 2]);
-  float gfin = 0.0f;
+  acc.r[2] = fmaf(dS, b.w, acc.r[2]);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    acc.r[2 + k] = fmaf(dS, E[k], acc.r[2 + k]);
-    const float e12 = e1[k] * e2[k];
-    gfin = fmaf(x.F[2 + k], e1[k] - e12, gfin);   // sum_k F_k dE_k/df_intra
-    // dE/dcos = cos e1 (-2b) (Dpar h - Dperp (1-fin) e2) = cos e1 (-2b) ((Dpar-Dperp) h + Dperp fin);
-    // the fibre's F_k multiplies the sums once per voxel, after the loop
-    const float t = fmaf(x.dpq, h[k], x.dqfin);
-    const float dc = (cc[k] * e1[k]) * t * dSz;
-    acc.r[Acc<K, LD>::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[Acc<K, LD>::kGd + 3 * k + 0]);
-    acc.r[Acc<K, LD>::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[Acc<K, LD>::kGd + 3 * k + 1]);
-    acc.r[Acc<K, LD>::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[Acc<K, LD>::kGd + 3 * k + 2]);
+    acc.r[AC::kE1 + k] = fmaf(dS, e1[k], acc.r[AC::kE1 + k]);
+    acc.r[AC::kE12 + k] = fmaf(dS, e12[k], acc.r[AC::kE12 + k]);
+    // dE/dcos = -2b cos (Dpar f_in e1 + (Dpar - Dperp)(1 - f_in) e12); the fibre's
+    // F_k multiplies the sums once per voxel, after the loop
+    const float t = fmaf(x.a1, e1[k], x.a2 * e12[k]);
+    const float dc = (cc[k] * dSz) * t;
+    acc.r[AC::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[AC::kGd + 3 * k + 0]);
+    acc.r[AC::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[AC::kGd + 3 * k + 1]);
+    acc.r[AC::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[AC::kGd + 3 * k + 2]);
     if (LD) {
-      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 e1 (1-fin) e2, with -b = (-2b)/2
-      const float dE = dS * x.F[2 + k];
+      // dE/dDpar = -b cos^2 E, dE/dDperp = -b sin^2 (1-fin) e12, with -b = (-2b)/2
       const float mb = 0.5f * c.z;
       const float c2 = cc[k] * cc[k];
-      acc.r[Acc<K, LD>::kDpar] = fmaf(dE * E[k], mb * c2, acc.r[Acc<K, LD>::kDpar]);
-      const float oe = x.omf * e2[k];
-      acc.r[Acc<K, LD>::kDperp] = fmaf(dE * e1[k] * oe, mb - mb * c2, acc.r[Acc<K, LD>::kDperp]);
+      const float FE = fmaf(x.Fa[k], e1[k], x.Fb[k] * e12[k]);
+      acc.r[AC::kDpar] = fmaf(dS * FE, mb * c2, acc.r[AC::kDpar]);
+      acc.r[AC::kDperp] = fmaf(dS * (x.Fb[k] * e12[k]), mb - mb * c2, acc.r[AC::kDperp]);
     }
   }
-  acc.r[Acc<K, LD>::kFin] = fmaf(dS, gfin, acc.r[Acc<K, LD>::kFin]);
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Measurements [nb, ne) for the VL voxels of this lane, in tiles of kTile.
-// The per-measurement sums over the wave's 64 x VL voxels (the alpha_n and
-// beta_n adjoints) are accumulated on the matrix core: with A = this lane's
+// The per-measurement sums over the wave's 64 x VL voxels (the beta_n adjoint,
+// and the alpha_n adjoint divided by exp(alpha_n), which multiplies the tile's
+// totals) are accumulated on the matrix core: with A = this lane's
 // partial and B = the one-hot column t = n - n0, v_mfma_f32_16x16x4f32 adds
 // each lane's value into column t of a 16x16 tile; after the tile, lane l
 // holds rows 4(l/16)..4(l/16)+3 of column l%16, so four adds and two lane
@@ -374,7 +405,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
     Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
     Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    sel = dpp_f32<0x111>(sel);  // row_shr:1 moves the one to lane16 == t + 1
+    sel = row_shr1_zero(sel);  // moves the one to lane16 == t + 1
   };
   auto tile_begin = [&]() {
     Da = v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -392,8 +423,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll
     for (int j = 0; j < VL; ++j) {
       float tl, ts, sq, sd;
-      pair_b0<MODE>(Fsum[j], acc[j].r[Acc<K, LD>::kLogB], dS0[j], slot[j], FULL ? 1.0f : valid[j], c, inv_s2,
-                    tl, ts, sq, sd);
+      pair_b0<MODE>(Fsum[j], dS0[j], slot[j], FULL ? 1.0f : valid[j], c, inv_s2, tl, ts, sq, sd);
       lacc += tl;
       if (MODE == kNLL) sacc += ts;
       pa = j == 0 ? sq : pa + sq;
@@ -404,14 +434,14 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
     Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
     Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    sel = dpp_f32<0x111>(sel);
+    sel = row_shr1_zero(sel);
   };
   // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
   auto group = [&](int t0) {
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
       body(t0 + u, yr[u]);
-      if ((u + 1) % sched_span(K, LD, VL) == 0) __builtin_amdgcn_sched_barrier(0);
+      if ((u + 1) % sched_span(K, MODE, LD, VL) == 0) __builtin_amdgcn_sched_barrier(0);
     }
   };
   // wave totals of the tile's per-measurement sums: lane l of the accumulator
@@ -424,7 +454,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     ra += __shfl_xor(ra, 32, 64);
     rb += __shfl_xor(rb, 32, 64);
     if (lane < cnt) {
-      wacc[n0 + lane] += ra;
+      wacc[n0 + lane] = fmaf(ra, acq[3 * (n0 + lane) + 2].x, wacc[n0 + lane]);  // times exp(alpha_n)
       wacc[N + n0 + lane] += rb;
     }
     dloss += (double)lacc;
@@ -437,7 +467,9 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     for (int j = 0; j < VL; ++j) {
       float sF = 0.0f;
 #pragma unroll
-      for (int cc = 0; cc < K + 3; ++cc) sF += x[j].F[cc];
+      for (int cc = 0; cc < 3; ++cc) sF += x[j].Fi[cc];
+#pragma unroll
+      for (int k = 0; k < K; ++k) sF += x[j].Fa[k] + x[j].Fb[k];
       Fsum[j] = sF;
       dS0[j] = 0.0f;
     }
@@ -454,7 +486,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll
     for (int j = 0; j < VL; ++j)
 #pragma unroll
-      for (int cc = 0; cc < K + 3; ++cc) acc[j].r[cc] += dS0[j];
+      for (int cc = 0; cc < 3 + 2 * K; ++cc) acc[j].r[cc] += dS0[j];  // e1 = e12 = 1
   }
   if (MODE == kMSE) {
     // whole tiles: every path into the loop has the ring's loads in flight in slot
@@ -494,10 +526,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 // variants a persistent kernel inlines)
 constexpr int kRecVals = 18;  // per-thread record values of the fused pass
 struct PassShared {
-  double red[4][kRecVals];
-  double ep_d[2][kBlock];   // per-thread repulsion / sparsity partials
-  float ep_f[4][kBlock];    // per-thread orphan / continuity / ordering / TV partials
-  float ep_b[10][kBlock];   // per-thread quadratic-bias adjoint partials
+  double wrec[4][kRecVals]; // per-wave record sums (the epilogue's terms added chunk by chunk)
   float adam_sc[2];         // fused Adam: step size and 1/sqrt(1 - b2^t)
 };
 
@@ -505,10 +534,7 @@ struct PassShared {
 template <int K, int MODE, bool LD, int VL>
 __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __restrict__ acq_global,
                                           const ItemDev& it, float4* smem4, PassShared& sh) {
-  auto& red = sh.red;
-  auto& ep_d = sh.ep_d;
-  auto& ep_f = sh.ep_f;
-  auto& ep_b = sh.ep_b;
+  auto& wrec = sh.wrec;
   constexpr int C = K + 3;
   constexpr int NACC = Acc<K, LD>::N;
   const GroupDev g = A.groups[it.group];
@@ -528,6 +554,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   const float4* acq_tab = acq;
 #endif
   for (int i = tid; i < 8 * N; i += kBlock) accab[i] = 0.0f;
+  if (lane < kRecVals) wrec[wave][lane] = 0.0;
   if (A.adam && tid == 0) adam_factors(A.step, A.lr, A.b1, A.b2, sh.adam_sc[0], sh.adam_sc[1], A.step_ready);
   __syncthreads();
 
@@ -541,14 +568,6 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   float* wacc = accab + wave * 2 * N;
 
   double dloss = 0.0, dsig = 0.0;
-  // per-thread partials of the epilogue (repulsion, sparsity, quadratic-bias adjoint),
-  // parked in LDS so that they are not live across the measurement loop
-  ep_d[0][tid] = 0.0;
-  ep_d[1][tid] = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ep_f[q][tid] = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 10; ++q) ep_b[q][tid] = 0.0f;
   bool bad_grad = false, zero_dir = false;
 
   const int chunk = 64 * VL * rows;
@@ -605,6 +624,13 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
     // epilogue: priors, chain rule to raw parameters, gradient store
     if (split == 0) {
+      // the chunk's epilogue terms per thread, summed over the wave after the chunk
+      // (so that nothing of them is live across the measurement loop)
+      double e_rep = 0.0, e_spa = 0.0;
+      float e_orph = 0.0f, e_cont = 0.0f, e_ord = 0.0f, e_tv = 0.0f;
+      float e_b[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) e_b[q] = 0.0f;
       float* gm = A.g_micro + g.micro_off;
       const float sc_rep = A.model.lam_rep * g.invM;
       const float sc_spa = A.model.lam_sparse * g.invM;
@@ -619,21 +645,35 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           bool zd = false;
           load_voxel<K, LD>(A, g, v, x_again, D, zd);
         }
+        using AC = Acc<K, LD>;
+        // sum_n dS E_c per compartment (fibres: f_in e1 + (1 - f_in) e12)
+        float aE[C];
+        aE[0] = acc[j].r[0];
+        aE[1] = acc[j].r[1];
+        aE[C - 1] = acc[j].r[2];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          aE[2 + k] = fmaf(D.fin, acc[j].r[AC::kE1 + k], D.omf * acc[j].r[AC::kE12 + k]);
+        const float BS0 = D.B * D.S0;
         float gF[C], gf[C];
-        float gS0 = 0.0f;
+        float gS0 = 0.0f, slb = 0.0f;
         const float sB = sdata * D.B;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          gF[c] = sB * acc[j].r[c];
+          gF[c] = sB * aE[c];
           gf[c] = D.S0 * gF[c];
           gS0 = fmaf(D.f[c], gF[c], gS0);
+          slb = fmaf(BS0 * D.f[c], aE[c], slb);   // sum_n seed (yhat - beta) = sum_c F_c sum dS E_c
         }
         float gd[K][3];
+        float sfin = 0.0f;                          // sum_k F_k sum dS dE_k/df_in
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float sF = sdata * x[j].F[2 + k];
+          const float Fk = BS0 * D.f[2 + k];
+          const float sF = sdata * Fk;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) gd[k][a] = sF * acc[j].r[Acc<K, LD>::kGd + 3 * k + a];
+          for (int a = 0; a < 3; ++a) gd[k][a] = sF * acc[j].r[AC::kGd + 3 * k + a];
+          sfin = fmaf(Fk, acc[j].r[AC::kE1 + k] - acc[j].r[AC::kE12 + k], sfin);
         }
         if (has_sp) {
           // Eq. 7 adjoint: w(x)|N(x)| - sum_{u in N(x)} w(u), weight rows [V][C]
@@ -688,7 +728,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
                 gd[k][a] = fmaf(w2, x[j].d[i][a], gd[k][a]);
               }
             }
-          ep_d[0][tid] += (double)lr;
+          e_rep += (double)lr;
         }
         if (g.priors & kPriorSparse) {
           float ls = 0.0f;
@@ -700,7 +740,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
               gf[2 + k] += sc_spa;
             }
           }
-          ep_d[1][tid] += (double)ls;
+          e_spa += (double)ls;
         }
         if (g.priors & kPriorOrphan) {
           // WM fractions where S0 is near zero: hinge max(0, 1 - S0/s0) on S0
@@ -714,7 +754,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
             gf[2 + k] = fmaf(sc, h, gf[2 + k]);
           }
           if (D.S0 < s0o) gS0 -= (sc / s0o) * wsum;
-          ep_f[0][tid] += h * wsum;
+          e_orph += h * wsum;
         }
         if (g.priors & kPriorOrder) {
           // fibre slots in descending order of fraction: hinge on each adjacent pair
@@ -729,7 +769,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
               gf[2 + k] -= sc;
             }
           }
-          ep_f[2][tid] += lo;
+          e_ord += lo;
         }
         if ((g.priors & kPriorCont) && g.nbh > 0) {
           // slot-wise alignment with the neighbours' directions; the pair (x, u)
@@ -760,7 +800,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
               gd[k][2] = fmaf(wd, dz, gd[k][2]);
             }
           }
-          ep_f[1][tid] += lc;
+          e_cont += lc;
         }
         // softmax chain rule
         float gsum = 0.0f;
@@ -777,7 +817,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           for (int a = 0; a < 3; ++a)
             gout[row_v(C, k, a)] = (gd[k][a] - pr * x[j].d[k][a]) * D.invn[k];
         }
-        gout[row_fin(C, K)] = x[j].fin * x[j].omf * sdata * acc[j].r[Acc<K, LD>::kFin];
+        gout[row_fin(C, K)] = D.fin * D.omf * sdata * sfin;
         if (LD) {
           gout[row_dpar(C, K)] = D.sig_dpar * sdata * acc[j].r[Acc<K, LD>::kDpar];
           gout[row_dpar(C, K) + 1] = D.sig_dperp * sdata * acc[j].r[Acc<K, LD>::kDperp];
@@ -824,7 +864,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           }
         }
         // bias-field adjoint dL/dlogB(x)
-        float glb = sdata * acc[j].r[Acc<K, LD>::kLogB];
+        float glb = sdata * slb;
         if ((g.priors & kPriorTV) && g.bias != 0) {
           // |B(x+e_a) - B(x)| over the in-mask face pairs: x owns the pair toward +e_a
           // and takes the derivative of both pairs it belongs to
@@ -848,7 +888,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
             }
           }
           glb = fmaf(A.model.lam_tv * g.invM, gt, glb);
-          ep_f[3][tid] += lt;
+          e_tv += lt;
         }
         if (g.bias == 1) {
           const int32_t pc = A.coords[g.vox_off + v];
@@ -859,10 +899,25 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           const float zz = fmaf((float)k, g.bsc[2], g.boff[2]);
           const float phi[10] = {1.0f, xx, yy, zz, xx * xx, yy * yy, zz * zz, xx * yy, xx * zz, yy * zz};
 #pragma unroll
-          for (int q = 0; q < 10; ++q) ep_b[q][tid] = fmaf(phi[q], glb, ep_b[q][tid]);
+          for (int q = 0; q < 10; ++q) e_b[q] = fmaf(phi[q], glb, e_b[q]);
         } else if (g.bias == 2) {
           A.wsp[g.glb_off + v] = glb;
         }
+      }
+      // record fields 1-6 and 8-17 (the terms this group has), wave-uniform branches
+      auto wadd = [&](int q, double x) {
+        const double t = wave_sum_f64(x);
+        if (lane == 0) wrec[wave][q] += t;
+      };
+      if (g.priors & kPriorRep) wadd(1, e_rep);
+      if (g.priors & kPriorSparse) wadd(2, e_spa);
+      if (g.priors & kPriorOrphan) wadd(3, (double)e_orph);
+      if ((g.priors & kPriorCont) && g.nbh > 0) wadd(4, (double)e_cont);
+      if (g.priors & kPriorOrder) wadd(5, (double)e_ord);
+      if ((g.priors & kPriorTV) && g.bias != 0) wadd(6, (double)e_tv);
+      if (g.bias == 1) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) wadd(8 + q, (double)e_b[q]);
       }
     }
     if (WN > 1) __syncthreads();  // xbuf is reused by the next chunk
@@ -870,25 +925,19 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
   // ---- item record: per-problem sums and per-measurement sums ----
   double* rec = A.rec + g.rec_off + (int64_t)it.rec * g.rec_stride;
-  double vals[kRecVals];
-  vals[0] = dloss;
-  vals[1] = ep_d[0][tid];
-  vals[2] = ep_d[1][tid];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) vals[3 + q] = (double)ep_f[q][tid];
-  vals[7] = dsig;
-#pragma unroll
-  for (int q = 0; q < 10; ++q) vals[8 + q] = (double)ep_b[q][tid];
-#pragma unroll
-  for (int q = 0; q < kRecVals; ++q) {
-    const double s = wave_sum_f64(vals[q]);
-    if (lane == 0) red[wave][q] = s;
+  {
+    const double sl = wave_sum_f64(dloss);
+    const double ss = wave_sum_f64(dsig);
+    if (lane == 0) {
+      wrec[wave][0] = sl;
+      wrec[wave][7] = ss;
+    }
   }
   if (bad_grad) atomicOr(A.status, (uint32_t)kStNonfiniteGrad);
   if (zero_dir) atomicOr(A.status, (uint32_t)kStZeroDir);
   __syncthreads();
   if (tid < kRecVals) {
-    const double s = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    const double s = wrec[0][tid] + wrec[1][tid] + wrec[2][tid] + wrec[3][tid];
     const int field = tid == 0 ? kRecData : tid == 1 ? kRecRep : tid == 2 ? kRecSparse
                       : tid < 7 ? kRecOrphan + (tid - 3) : tid == 7 ? kRecSigma
                       : kRecBias + (tid - 8);
@@ -904,7 +953,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 
 // One block per item of one kernel variant.
 template <int K, int MODE, bool LD, int VL>
-__global__ __launch_bounds__(kBlock, pass_min_waves(K, LD, VL)) void k_pass(
+__global__ __launch_bounds__(kBlock, pass_min_waves(K, MODE, LD, VL)) void k_pass(
     PassArgs A, const float4* __restrict__ acq_global) {
   extern __shared__ float4 smem4[];
   __shared__ PassShared sh;
@@ -933,17 +982,18 @@ __global__ __launch_bounds__(kBlock) void k_synth(PassArgs A) {
     load_voxel<K, LD>(A, g, v, x, dv, zero_dir);
     for (int n = 0; n < g.N; ++n) {
       const float4 a = acq[3 * n], b = acq[3 * n + 1], c = acq[3 * n + 2];
-      float S = x.F[0] * b.y;
-      S = fmaf(x.F[1], b.z, S);
-      S = fmaf(x.F[K + 2], b.w, S);
+      float S = x.Fi[0] * b.y;
+      S = fmaf(x.Fi[1], b.z, S);
+      S = fmaf(x.Fi[2], b.w, S);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const float cc = fmaf(a.z, x.d[k][2], fmaf(a.y, x.d[k][1], a.x * x.d[k][0]));
         const float c2 = cc * cc;
         const float kp = LD ? a.w * x.dpar : a.w;
         const float kq = LD ? b.x * x.dperp : b.x;
-        const float E = ex2(kp * c2) * (x.fin + x.omf * ex2(fmaf(-kq, c2, kq)));
-        S = fmaf(x.F[2 + k], E, S);
+        const float kd = LD ? kp - kq : c.w;
+        S = fmaf(x.Fa[k], ex2(kp * c2), S);
+        S = fmaf(x.Fb[k], ex2(fmaf(kd, c2, kq)), S);
       }
       out[(int64_t)n * V + v] = fmaf(c.x, S, c.y);
     }
@@ -964,7 +1014,7 @@ inline size_t pass_lds_bytes(int maxN, int xsplit, int nacc_, int vpl) {
 
 template <int K, int MODE, bool LD, int VL>
 static hipError_t launch_pass_t(const PassArgs& a, hipStream_t s, int maxN) {
-  const size_t lds = pass_lds_bytes(maxN, a.n_split, (K + 3) + 3 * K + 2 + (LD ? 2 : 0), VL);
+  const size_t lds = pass_lds_bytes(maxN, a.n_split, acc_count(K, LD), VL);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pass<K, MODE, LD, VL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -58,7 +58,7 @@ __global__ void k_counter_reset(int32_t* counter) {
 hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
                                   hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  const size_t lds = pass_lds_bytes(maxN, a.n_split, (kMaxK + 3) + 3 * kMaxK + 4, 1);
+  const size_t lds = pass_lds_bytes(maxN, a.n_split, acc_count(kMaxK, true), 1);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_pass_persistent,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -73,7 +73,7 @@ hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t
 }
 
 int persistent_blocks_per_cu(int maxN, int xsplit) {
-  const size_t lds = pass_lds_bytes(maxN, xsplit, (kMaxK + 3) + 3 * kMaxK + 4, 1);
+  const size_t lds = pass_lds_bytes(maxN, xsplit, acc_count(kMaxK, true), 1);
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_persistent, kBlock, lds) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
