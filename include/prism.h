@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PRISM_ABI_VERSION 3
+#define PRISM_ABI_VERSION 4
 #define PRISM_MAX_K 6
 #define PRISM_MAX_MEAS 1024
 #define PRISM_MAX_EDGE 1023
@@ -293,12 +293,18 @@ int32_t prism_adam_step(float* p, const float* g, float* m, float* v, int64_t n,
  * per-voxel gradient.  Arguments as for prism_loss_grad and prism_adam_step;
  * m_micro, v_micro [n_micro] and m_cal, v_cal [n_cal] are the Adam moments
  * (device), grad_micro [n_micro] (device) is scratch for the unfused case,
- * grad_cal [n_cal] receives the calibration gradient.  Asynchronous;
- * allocates nothing; graph-capturable. */
+ * grad_cal [n_cal] receives the calibration gradient.
+ *   loss_history  NULL, or a device float64 ring [history_len][n_groups]
+ *                 [PRISM_LOSS_TERMS]: the call also writes its loss rows to
+ *                 slot t mod history_len, t = the iteration's index (step[0]
+ *                 before the call), so that a graph-captured loop keeps the
+ *                 whole loss history on the device; history_len >= 1 then.
+ * Asynchronous; allocates nothing; graph-capturable. */
 int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* theta_micro,
                              float* theta_cal, float* m_micro, float* v_micro, float* m_cal,
                              float* v_cal, int32_t* step, float lr, float beta1, float beta2,
-                             float eps, int32_t update_cal, double* loss, float* grad_micro,
+                             float eps, int32_t update_cal, double* loss, double* loss_history,
+                             int32_t history_len, float* grad_micro,
                              float* grad_cal, void* workspace, size_t workspace_bytes,
                              uint32_t* status, void* stream);
 

@@ -108,8 +108,8 @@ SIGNATURES = {
     "prism_loss_grad_noalloc": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "prism_adam_step": (_I32, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P, _P]),
     "prism_rprop_step": (_I32, [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _P]),
-    "prism_iteration_adam": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _F, _F, _F, _F, _I32, _P, _P, _P,
-                                    _P, ctypes.c_size_t, _P, _P]),
+    "prism_iteration_adam": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _F, _F, _F, _F, _I32, _P, _P, _I32,
+                                    _P, _P, _P, ctypes.c_size_t, _P, _P]),
     "prism_rician_terms": (_I32, [_P, _P, _P, _P, _I64, _P]),
     "prism_stitch_plan": (_I32, [_P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_int64)]),

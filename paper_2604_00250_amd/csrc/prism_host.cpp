@@ -768,9 +768,18 @@ struct CalAdam {
   int update;  // 0: theta_cal held fixed (the counter still advances)
 };
 
+// loss-history ring of a fused iteration (see prism_iteration_adam)
+struct History {
+  double* ring;
+  const int32_t* step;
+  int32_t len;
+  int32_t adv;  // 1 when step[0] has already advanced when the loss rows are written
+};
+
 int run_pass(const prism_problem* h, const float* y, const float* theta_micro, const float* theta_cal,
              double* loss, float* grad_micro, float* grad_cal, void* workspace, uint32_t* status,
-             hipStream_t s, const PassArgs* adam, const CalAdam* cal_adam = nullptr) {
+             hipStream_t s, const PassArgs* adam, const CalAdam* cal_adam = nullptr,
+             const History* hist = nullptr) {
   char* ws = (char*)workspace;
   const size_t o_part = align256(h->ws_rec * sizeof(double));
   const size_t o_float = o_part + align256(h->ws_part * sizeof(double));
@@ -854,6 +863,12 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     r.b2 = cal_adam->b2;
     r.eps = cal_adam->eps;
   }
+  if (hist && hist->ring) {
+    r.hist = hist->ring;
+    r.hist_step = hist->step;
+    r.hist_len = hist->len;
+    r.hist_adv = hist->adv;
+  }
   e = launch_reduce(r, h->max_field_chunks, s);
   if (e != hipSuccess) return hip_fail(e, "reduction launch");
   e = launch_bias_trilinear(r, h->d_tri, (int)h->tri_groups.size(), s);
@@ -914,12 +929,13 @@ int32_t prism_loss_grad_noalloc(const prism_problem* h, const float* y, const fl
 int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* theta_micro,
                              float* theta_cal, float* m_micro, float* v_micro, float* m_cal,
                              float* v_cal, int32_t* step, float lr, float beta1, float beta2,
-                             float eps, int32_t update_cal, double* loss, float* grad_micro,
-                             float* grad_cal, void* workspace, size_t workspace_bytes,
-                             uint32_t* status, void* stream) {
+                             float eps, int32_t update_cal, double* loss, double* loss_history,
+                             int32_t history_len, float* grad_micro, float* grad_cal, void* workspace,
+                             size_t workspace_bytes, uint32_t* status, void* stream) {
   int rc = check_pass_args(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace,
                            workspace_bytes, status);
   if (rc != PRISM_OK) return rc;
+  if (loss_history && history_len < 1) return fail(PRISM_E_INVALID, "history_len must be >= 1");
   if (!step || (h->n_micro && (!m_micro || !v_micro)) || (update_cal && (!m_cal || !v_cal)))
     return fail(PRISM_E_INVALID, "NULL device pointer");
   if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
@@ -942,7 +958,9 @@ int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* thet
     ad.b2 = beta2;
     ad.eps = eps;
     CalAdam ca{theta_cal, m_cal, v_cal, step, lr, beta1, beta2, eps, update_cal ? 1 : 0};
-    return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad, &ca);
+    const History hi{loss_history, step, history_len, 1};  // the first kernel advanced step[0]
+    return run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad, &ca,
+                    &hi);
   }
   if (fuse) {
     PassArgs ad{};
@@ -954,10 +972,14 @@ int32_t prism_iteration_adam(const prism_problem* h, const float* y, float* thet
     ad.b1 = beta1;
     ad.b2 = beta2;
     ad.eps = eps;
-    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad);
+    const History hi{loss_history, step, history_len, 0};  // advanced by the Adam launch below
+    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, &ad, nullptr,
+                  &hi);
     if (rc != PRISM_OK) return rc;
   } else {
-    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, nullptr);
+    const History hi{loss_history, step, history_len, 0};
+    rc = run_pass(h, y, theta_micro, theta_cal, loss, grad_micro, grad_cal, workspace, status, s, nullptr,
+                  nullptr, &hi);
     if (rc != PRISM_OK) return rc;
     hipError_t e = launch_adam(theta_micro, grad_micro, m_micro, v_micro, h->n_micro, lr, beta1, beta2, eps,
                                step, s, false);

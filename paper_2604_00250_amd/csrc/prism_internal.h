@@ -139,6 +139,11 @@ struct ReduceArgs {
   const int32_t* step;
   float lr, b1, b2, eps;
   const double* calsq;     // precomputed [n_groups][3] (the cal prior's loss) or nullptr
+  // loss-history ring [hist_len][n_groups][terms] (or nullptr): the loss rows also go
+  // to slot (hist_step[0] - hist_adv) mod hist_len, the iteration's index
+  double* hist;
+  const int32_t* hist_step;
+  int32_t hist_len, hist_adv;
 };
 
 struct StitchArgs {

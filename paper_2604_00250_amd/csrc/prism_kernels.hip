@@ -392,6 +392,13 @@ __global__ __launch_bounds__(256) void k_reduce2(ReduceArgs R) {
     L[8] = tv;
     L[9] = data + sp + rp + sa + orp + cnt + ord + cl + tv;
     if (!isfinite(L[9])) atomicOr(R.status, (uint32_t)kStNonfiniteLoss);
+    if (R.hist) {
+      int slot = (R.hist_step[0] - R.hist_adv) % R.hist_len;
+      if (slot < 0) slot += R.hist_len;
+      double* H = R.hist + ((int64_t)slot * R.n_groups + gi) * kLossTerms;
+#pragma unroll
+      for (int i = 0; i < kLossTerms; ++i) H[i] = L[i];
+    }
   }
 }
 

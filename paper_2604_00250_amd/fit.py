@@ -45,22 +45,18 @@ class Loop:
             self.rstep = torch.full((n,), lr, dtype=torch.float32, device=dev)
             self.it = torch.zeros(1, dtype=torch.int64, device=dev)
 
-    def _record(self, after_step=False):
-        # history slot = the iteration's index (device counter of completed steps,
-        # already advanced when the step ran first), modulo the ring length
-        if self.optimizer == "adam":
-            idx = self.st.step[:1].to(torch.int64) - (1 if after_step else 0)
-        else:
-            idx = self.it
-        idx = torch.remainder(idx, self.hist_len)
+    def _record(self):
+        # Rprop: history slot = the iteration's index (device counter), modulo the ring length
+        idx = torch.remainder(self.it, self.hist_len)
         self.hist.index_copy_(0, idx, self.st.loss.unsqueeze(0))
 
     def step_eager(self):
         st = self.st
         if self.optimizer == "adam":
-            # one call: loss at the current parameters, then the Adam step
-            st.iteration(self.lr, self.betas[0], self.betas[1], self.eps, update_cal=self.calibrate)
-            self._record(after_step=True)
+            # one call: loss at the current parameters (also written by the library to
+            # the history row of this iteration), then the Adam step
+            st.iteration(self.lr, self.betas[0], self.betas[1], self.eps, update_cal=self.calibrate,
+                         history=self.hist)
             return
         st.loss_grad()
         self._record()

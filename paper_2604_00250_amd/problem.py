@@ -194,11 +194,12 @@ class Problem:
                                                 status, stream))
 
     def iteration_adam_ptr(self, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal, step, lr, b1, b2, eps,
-                           update_cal, loss, g_micro, g_cal, ws, ws_bytes, status, stream):
+                           update_cal, loss, g_micro, g_cal, ws, ws_bytes, status, stream, hist=None,
+                           hist_len=0):
         L.check(L.lib().prism_iteration_adam(self.handle, y, th_micro, th_cal, m_micro, v_micro, m_cal, v_cal,
                                              step, float(lr), float(b1), float(b2), float(eps),
-                                             int(bool(update_cal)), loss, g_micro, g_cal, ws, ws_bytes,
-                                             status, stream))
+                                             int(bool(update_cal)), loss, hist, int(hist_len), g_micro, g_cal,
+                                             ws, ws_bytes, status, stream))
 
     def synthesize_ptr(self, th_micro, th_cal, yhat, stream):
         L.check(L.lib().prism_synthesize(self.handle, th_micro, th_cal, yhat, stream))
@@ -310,15 +311,22 @@ class DeviceState:
         adam_step_ptr(self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                       n, lr, beta1, beta2, eps, self.step.data_ptr(), self._s())
 
-    def iteration(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, update_cal=True):
+    def iteration(self, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, update_cal=True, history=None):
         """One Adam iteration through prism_iteration_adam (the per-voxel update
-        runs inside the fused pass); self.loss holds the loss before the step."""
+        runs inside the fused pass); self.loss holds the loss before the step.
+        history: optional float64 device tensor [L][n_groups][10]; the loss rows
+        also go to row (iteration index mod L), written by the library."""
         pm, pc, gm, gc = self.ptrs()
         m, v = self.m.data_ptr(), self.v.data_ptr()
+        hp, hl = (history.data_ptr(), history.shape[0]) if history is not None else (None, 0)
+        if history is not None:
+            if (history.dtype != self.torch.float64 or history.device != self.device or not history.is_contiguous()
+                    or tuple(history.shape[1:]) != (self.prob.n_groups, len(L.LOSS_TERMS))):
+                raise ValueError("history must be a contiguous float64 device tensor [L][n_groups][10]")
         self.prob.iteration_adam_ptr(self.y.data_ptr(), pm, pc, m, v, m + 4 * self.n_micro, v + 4 * self.n_micro,
                                      self.step.data_ptr(), lr, beta1, beta2, eps, update_cal,
                                      self.loss.data_ptr(), gm, gc, self.ws.data_ptr(), self.ws_bytes,
-                                     self.status.data_ptr(), self._s())
+                                     self.status.data_ptr(), self._s(), hist=hp, hist_len=hl)
 
     def iteration_unfused(self, lr=1e-2):
         """The same iteration as prism_loss_grad followed by prism_adam_step."""

@@ -29,7 +29,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
         assert n in L.SIGNATURES, f"binding misses {n}"
-    assert lib.prism_abi_version() == 3
+    assert lib.prism_abi_version() == 4
 
 
 def test_model_defaults_are_the_papers_constants():
@@ -153,7 +153,7 @@ def test_null_handles_and_optimiser_arguments():
     assert lib.prism_rprop_step(fake, fake, fake, fake, 10, 0.5, 0.9, 1e-6, 50.0, None) == L.PRISM_E_INVALID
     assert lib.prism_profile_enable(None, 1, 4) == L.PRISM_E_INVALID
     assert lib.prism_iteration_adam(None, None, None, None, None, None, None, None, None, 1e-2, 0.9, 0.999, 1e-8,
-                                    1, None, None, None, None, 0, None, None) == L.PRISM_E_INVALID
+                                    1, None, None, 0, None, None, None, 0, None, None) == L.PRISM_E_INVALID
     assert lib.prism_stitch_plan(None, 4, 4, 4, None, None) == L.PRISM_E_INVALID
     assert lib.prism_stitch_maps(None, None, None, None) == L.PRISM_E_INVALID
     assert "NULL" in lib.prism_last_error().decode() or "handle" in lib.prism_last_error().decode()

@@ -88,6 +88,32 @@ def test_graph_replay_equals_eager_iterations_bitwise():
     assert tot[-1] < tot[0]
 
 
+def test_library_loss_history_rows_are_each_iterations_loss():
+    """prism_iteration_adam writes each iteration's loss rows into the history
+    ring at (iteration index mod length): the fused path, the fused path with
+    the calibration held fixed, and the unfused path that a continuity prior
+    forces; seven iterations on a ring of three rows."""
+    import torch
+    base = dict(shape=(7, 6, 6), K=2, mode="mse", acq_kind="two96", bias="poly2")
+    cases = [("fused", masked_group(seed=61, priors=("spatial", "rep", "cal"), **base), True),
+             ("fused, calibration fixed", masked_group(seed=62, priors=("spatial", "rep", "cal"), **base), False),
+             ("unfused (continuity)", masked_group(seed=63, priors=("spatial", "continuity", "cal"), **base), True)]
+    for name, g, cal in cases:
+        st = _state([g])
+        hist = torch.full((3, 1, 10), float("nan"), dtype=torch.float64, device=st.device)
+        rows = []
+        for t in range(7):
+            st.iteration(1e-2, update_cal=cal, history=hist)
+            torch.cuda.synchronize()
+            rows.append(st.loss.clone())
+            assert torch.equal(hist[t % 3], rows[t]), f"{name}: iteration {t}"
+        assert int(st.step[0].item()) == 7
+        for t in (4, 5, 6):
+            assert torch.equal(hist[t % 3], rows[t])
+        say(f"[history {name}] totals {[float(r[0, 9]) for r in rows]}")
+        assert float(rows[-1][0, 9]) < float(rows[0][0, 9])
+
+
 def test_rprop_loop_graph_equals_eager():
     import torch
     from paper_2604_00250_amd.fit import Loop, restore, snapshot
