@@ -94,14 +94,51 @@ __device__ __forceinline__ float lane63(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
 }
 
-__device__ __forceinline__ double wave_sum_f64(double x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-  return x;
+// Lane exchanges across rows without per-use index arithmetic: ds_swizzle in
+// bitmask mode (and-mask 0x1f, xor-mask 16: lane i reads lane i ^ 16 within
+// each half-wave) and ds_bpermute from lane i ^ 32.  Full waves only.
+__device__ __forceinline__ int xor16_b32(int x) { return __builtin_amdgcn_ds_swizzle(x, 0x401F); }
+__device__ __forceinline__ int xor32_b32(int x) {
+  return __builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32u) << 2), x);
 }
-__device__ __forceinline__ float wave_sum_f32_all(float x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+__device__ __forceinline__ float xor16_f32(float x) {
+  return __builtin_bit_cast(float, xor16_b32(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ float xor32_f32(float x) {
+  return __builtin_bit_cast(float, xor32_b32(__builtin_bit_cast(int, x)));
+}
+
+// A float64 through a DPP pattern (both halves; every lane of the patterns
+// used here has a valid source)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double xor16_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)xor16_b32((int)(uint32_t)u), hi = (uint32_t)xor16_b32((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double xor32_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)xor32_b32((int)(uint32_t)u), hi = (uint32_t)xor32_b32((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a full wave, the same total in every lane: within
+// rows of 16 by DPP (quad_perm xor 1, xor 2, half-row mirror, row mirror, each
+// leaving its group uniform), then rows 0+1 and 2+3 (xor 16), then the halves
+// (xor 32).  A fixed order, so the result is reproducible bit for bit.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141>(x);  // row_half_mirror
+  x += dpp_f64<0x140>(x);  // row_mirror
+  x += xor16_f64(x);
+  x += xor32_f64(x);
   return x;
 }
 

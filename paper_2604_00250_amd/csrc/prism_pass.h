@@ -449,10 +449,10 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
   auto tile_end = [&](int cnt) {
     float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);
     float rb = (Db[0] + Db[1]) + (Db[2] + Db[3]);
-    ra += __shfl_xor(ra, 16, 64);
-    rb += __shfl_xor(rb, 16, 64);
-    ra += __shfl_xor(ra, 32, 64);
-    rb += __shfl_xor(rb, 32, 64);
+    ra += xor16_f32(ra);
+    rb += xor16_f32(rb);
+    ra += xor32_f32(ra);
+    rb += xor32_f32(rb);
     if (lane < cnt) {
       wacc[n0 + lane] = fmaf(ra, acq[3 * (n0 + lane) + 2].x, wacc[n0 + lane]);  // times exp(alpha_n)
       wacc[N + n0 + lane] += rb;
