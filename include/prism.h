@@ -179,6 +179,16 @@ typedef struct {
   int32_t max_blocks;   /* persistent launch: at most this many blocks (0 = as many
                            as the device holds at once); fewer blocks than work items
                            make each block run several items in turn */
+  int32_t stagger;      /* 1 (the default): a problem of one large group cut into
+                           one-chunk items (vox_per_lane 1, n_split 1, item_vox 0)
+                           starts every XCD's run of items with CUs/8 shorter items
+                           (half of 64 voxels over four waves, half of 128 over two),
+                           so that one block per compute unit runs out of phase with
+                           the others and the blocks' epilogue memory traffic does
+                           not arrive all at once; 0: equal items only.  Ignored
+                           where it does not apply (several groups, other shapes,
+                           fewer than two rounds of blocks, or when the measurement
+                           split's LDS would cost the variant a block per CU). */
 } prism_launch;
 
 /* Launch shape of one bucket of groups: those with n_meas measurements, K

@@ -164,6 +164,10 @@ hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
                                   hipStream_t s);
 int persistent_blocks_per_cu(int maxN, int xsplit);
+// launch facts of the fused pass's per-variant kernels: LDS bytes per block (static
+// and dynamic) and the waves per SIMD its register budget allows
+size_t pass_lds_per_block(int maxN, int xsplit, int K, int learn_d, int vpl);
+int pass_waves_per_simd(int K, int mode, int learn_d, int vpl);
 // every fused-pass variant of one K (one translation unit per K)
 template <int K>
 hipError_t launch_pass_k(const PassArgs& a, int mode, int learn_d, int vpl, int maxN, hipStream_t s);

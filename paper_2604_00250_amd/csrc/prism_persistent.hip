@@ -79,6 +79,14 @@ int persistent_blocks_per_cu(int maxN, int xsplit) {
   return nb > 0 ? nb : 1;
 }
 
+size_t pass_lds_per_block(int maxN, int xsplit, int K, int learn_d, int vpl) {
+  return sizeof(PassShared) + pass_lds_bytes(maxN, xsplit, acc_count(K, learn_d != 0), vpl);
+}
+
+int pass_waves_per_simd(int K, int mode, int learn_d, int vpl) {
+  return pass_min_waves(K, mode, learn_d != 0, vpl);
+}
+
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s) {
   // only the scalar-cache variant of k_pass reads the global table
   if (n_groups <= 0 || !PRISM_ACQ_SMEM) return hipSuccess;

@@ -98,6 +98,23 @@ def test_brain_volume_full_size(perturb_seed):
         worst[k] = int(np.argmax(np.abs(a - b).max(0)))
     H.say(f"[full] per-voxel gradient errors over all {V} voxels {errs}; worst voxels {worst}")
     assert max(errs.values()) <= 1e-4
+    # the default plan is the staggered cut (more items than equal 256-voxel ones);
+    # the plain cut of equal items against the same oracle values
+    n_equal = -(-V // 256)
+    assert prob.plan_info()["items"] > n_equal, prob.plan_info()
+    prob.tune(vox_per_lane=1, n_split=1, item_vox=0, stagger=0)
+    st.resize_workspace()
+    assert prob.plan_info()["items"] == n_equal
+    st.loss_grad()
+    torch.cuda.synchronize()
+    loss0 = st.loss_host()[0]
+    gm0, gc0 = st.grads_host()
+    assert int(st.status.item()) == 0
+    assert abs(loss0[9] - ref["total"]) <= 1e-5 * abs(ref["total"])
+    errs0 = H.class_errors({k: gm0[0][k] for k in full_ref}, full_ref)
+    errs0.update(H.class_errors(gc0[0], dict(alpha=g_alpha + ga, beta=g_beta + gb, bias=g_bias + gw)))
+    H.say(f"[full] equal-item plan {prob.plan_info()}: loss {loss0[9]:.10g}; gradient errors {errs0}")
+    assert max(errs0.values()) <= 1e-4
 
 
 @pytest.mark.timeout(300)
