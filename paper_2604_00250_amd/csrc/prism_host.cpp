@@ -553,6 +553,21 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
     while (g.nb0 < g.N && bval[(size_t)g.acq_off + g.nb0] == 0.0f) ++g.nb0;
     g.rec_stride = kRecHead + 2 * g.N;
     g.invM = V > 0 ? 1.0f / (float)V : 0.0f;
+    {
+      const ModelDev& m = h->model;
+      g.sdata = g.mode == PRISM_MSE ? 2.0f * g.invM : 1.0f;
+      g.sc_sp = m.lam_sp * g.invM;
+      g.sc_rep = m.lam_rep * g.invM;
+      g.sc_spa = m.lam_sparse * g.invM;
+      g.sc_orph = m.lam_orphan * g.invM;
+      g.sc_ord = m.lam_order * g.invM;
+      g.sc_tv = m.lam_tv * g.invM;
+      g.sc_cont2 = -2.0f * m.lam_cont * g.invM;
+      g.inv_s0o = 1.0f / m.s0_orphan;
+      g.sc_orph_s0 = g.sc_orph / m.s0_orphan;
+      const int32_t n3[3] = {d.nx, d.ny, d.nz};
+      for (int a = 0; a < 3; ++a) g.tri_sc[a] = n3[a] > 1 ? 7.0f / (float)(n3[a] - 1) : 0.0f;
+    }
     g.ntab = ntab;
     g.nbr_off = (int64_t)nbr.size();
     g.ninv_off = (int64_t)ninv.size();

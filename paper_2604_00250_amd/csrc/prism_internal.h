@@ -55,6 +55,15 @@ struct GroupDev {
   int32_t item_begin, item_count;
   int32_t tile_begin, tile_count;  // first-stage reduction tiles of this group
   float invM;         // 1/|M| (0 when the group is empty)
+  // per-group float constants of the fused pass, formed once on the host (the
+  // device has no scalar float unit: formed in the kernel they would sit in
+  // vector registers across the measurement loop)
+  float sdata;        // scale of the data term's seed: 2/|M| (MSE) or 1 (NLL)
+  float sc_sp, sc_rep, sc_spa, sc_orph, sc_ord, sc_tv;  // prior weights lam/|M|
+  float sc_cont2;     // -2 lam_cont / |M|
+  float inv_s0o;      // 1 / s0_orphan
+  float sc_orph_s0;   // lam_orphan / |M| / s0_orphan
+  float tri_sc[3];    // 7 / (n_a - 1): trilinear control-grid coordinate per voxel step (0 if n_a = 1)
 };
 
 struct ItemDev {

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void k_bias_tri(ReduceArgs R, const int32_t* t
       float w = 1.0f;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const float p = nn[a] > 1 ? ii[a] * (7.0f / (float)(nn[a] - 1)) : 0.0f;
+        const float p = ii[a] * g.tri_sc[a];  // the coordinate of log_bias, bit for bit
         w *= fmaxf(0.0f, 1.0f - fabsf(p - (float)cidx[a]));
       }
       acc += (double)w * (double)glb[v];

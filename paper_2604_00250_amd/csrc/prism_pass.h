@@ -148,10 +148,9 @@ __device__ __forceinline__ float log_bias(const GroupDev& g, const float* cal, i
   float p[3];
   int i0[3];
   const int ii[3] = {i, j, k};
-  const int nn[3] = {g.nx, g.ny, g.nz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float pa = nn[a] > 1 ? ii[a] * (7.0f / (float)(nn[a] - 1)) : 0.0f;
+    const float pa = ii[a] * g.tri_sc[a];
     int c = (int)floorf(pa);
     c = c > 6 ? 6 : c;
     i0[a] = c;
@@ -458,7 +457,7 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
       wacc[N + n0 + lane] += rb;
     }
     dloss += (double)lacc;
-    dsig += (double)sacc;
+    if (MODE == kNLL) dsig += (double)sacc;  // 0 for MSE
   };
   // whole tiles of the acquisition's leading b = 0 measurements first
   const int b0end = min(nb0, ne);
@@ -563,7 +562,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
   const float* yg = A.y + g.y_off;
   const float* cal = A.th_cal + g.cal_off;
   const float inv_s2 = MODE == kNLL ? expf(-2.0f * cal[g.n_bias + 2 * N]) : 0.0f;
-  const float sdata = MODE == kMSE ? 2.0f * g.invM : 1.0f;
+  const float sdata = g.sdata;
   const bool has_sp = (g.priors & kPriorSpatial) && g.nbh > 0;
   float* wacc = accab + wave * 2 * N;
 
@@ -632,9 +631,9 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
       for (int q = 0; q < 10; ++q) e_b[q] = 0.0f;
       float* gm = A.g_micro + g.micro_off;
-      const float sc_rep = A.model.lam_rep * g.invM;
-      const float sc_spa = A.model.lam_sparse * g.invM;
-      const float sc_sp = A.model.lam_sp * g.invM;
+      const float sc_rep = g.sc_rep;
+      const float sc_spa = g.sc_spa;
+      const float sc_sp = g.sc_sp;
 #pragma unroll
       for (int j = 0; j < VL; ++j) {
         if (valid[j] == 0.0f) continue;
@@ -745,20 +744,20 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
         if (g.priors & kPriorOrphan) {
           // WM fractions where S0 is near zero: hinge max(0, 1 - S0/s0) on S0
           const float s0o = A.model.s0_orphan;
-          const float sc = A.model.lam_orphan * g.invM;
-          const float h = fmaxf(0.0f, 1.0f - D.S0 / s0o);
+          const float sc = g.sc_orph;
+          const float h = fmaxf(0.0f, fmaf(-D.S0, g.inv_s0o, 1.0f));
           float wsum = 0.0f;
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             wsum += D.f[2 + k];
             gf[2 + k] = fmaf(sc, h, gf[2 + k]);
           }
-          if (D.S0 < s0o) gS0 -= (sc / s0o) * wsum;
+          if (D.S0 < s0o) gS0 -= g.sc_orph_s0 * wsum;
           e_orph += h * wsum;
         }
         if (g.priors & kPriorOrder) {
           // fibre slots in descending order of fraction: hinge on each adjacent pair
-          const float sc = A.model.lam_order * g.invM;
+          const float sc = g.sc_ord;
           float lo = 0.0f;
 #pragma unroll
           for (int k = 0; k + 1 < K; ++k) {
@@ -777,7 +776,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           const int32_t* nbr = A.nbr + g.nbr_off;
           const float* ninv = A.ninv + g.ninv_off;
           const float* th = A.th_micro + g.micro_off;
-          const float sc2 = -2.0f * A.model.lam_cont * g.invM;
+          const float sc2 = g.sc_cont2;
           const float ax = ninv[v];
           float lc = 0.0f;
           for (int q = 0; q < g.nbh; ++q) {
@@ -887,7 +886,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
               gt += dl > 0.0f ? B0 : (dl < 0.0f ? -B0 : 0.0f);
             }
           }
-          glb = fmaf(A.model.lam_tv * g.invM, gt, glb);
+          glb = fmaf(g.sc_tv, gt, glb);
           e_tv += lt;
         }
         if (g.bias == 1) {
