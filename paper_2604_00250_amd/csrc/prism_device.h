@@ -48,6 +48,31 @@ __device__ __forceinline__ float load_row_f32(const float* row, uint32_t nbytes,
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// The same for a store, and for an int32 row.  A parameter-major block [P][V]
+// is P such rows of V entries (V <= 1023^3, so V * 4 < 2^32): every lane
+// addresses every row with one 32-bit offset (its voxel * 4) and the row bases
+// stay uniform, where 64-bit per-lane addresses take two registers per row.
+__device__ __forceinline__ void store_row_f32(float* row, uint32_t nbytes, uint32_t off, float x) {
+  __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(row, (short)0, (int)nbytes, 0x00020000);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, off, 0, 0);
+}
+__device__ __forceinline__ int32_t load_row_i32(const int32_t* row, uint32_t nbytes, uint32_t off) {
+  __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<int32_t*>(row), (short)0, (int)nbytes, 0x00020000);
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// Row `row` of a [rows][V] block, its base pinned in scalar registers where it
+// is used (an empty asm statement), so that the compiler builds each row's
+// buffer descriptor at its access instead of hoisting the descriptors of every
+// row (four scalar registers each) out of the loops around them, which spilled.
+template <typename T>
+__device__ __forceinline__ T* row_base(T* base, int64_t row, int64_t V) {
+  T* p = base + row * V;
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // Work item of block b in a launch of n blocks.  The dispatcher deals blocks
 // to the 8 XCDs in turn (block b to XCD b mod 8) and each XCD has its own L2;
 // giving XCD x one contiguous run of items keeps the neighbours that an item

@@ -180,14 +180,16 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
   constexpr int C = K + 3;
   const float* th = A.th_micro + g.micro_off;
   const int64_t V = g.V;
-  const float s = th[v];
+  const uint32_t rowb = (uint32_t)V * 4u, off = (uint32_t)v * 4u;  // rows of V floats
+  auto at = [&](int row) { return load_row_f32(row_base(th, row, V), rowb, off); };
+  const float s = at(0);
   dv.S0 = softplus_f(s);
   dv.sig_s = sigmoid_f(s);
   float lg[C];
   float m = -INFINITY;
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    lg[c] = th[(int64_t)row_logit(c) * V + v];
+    lg[c] = at(row_logit(c));
     m = fmaxf(m, lg[c]);
   }
   float sum = 0.0f;
@@ -204,9 +206,9 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
   for (int c = 0; c < C; ++c) dv.f[c] = lg[c] * inv;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float vx = th[(int64_t)row_v(C, k, 0) * V + v];
-    const float vy = th[(int64_t)row_v(C, k, 1) * V + v];
-    const float vz = th[(int64_t)row_v(C, k, 2) * V + v];
+    const float vx = at(row_v(C, k, 0));
+    const float vy = at(row_v(C, k, 1));
+    const float vz = at(row_v(C, k, 2));
     const float n2 = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
     float in = 0.0f;
     if (n2 > 0.0f) {
@@ -219,7 +221,7 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     x.d[k][1] = vy * in;
     x.d[k][2] = vz * in;
   }
-  const float fin = sigmoid_f(th[(int64_t)row_fin(C, K) * V + v]);
+  const float fin = sigmoid_f(at(row_fin(C, K)));
   const float omf = 1.0f - fin;
   dv.fin = fin;
   dv.omf = omf;
@@ -233,8 +235,8 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     x.Fb[k] = F * omf;
   }
   if (LD) {
-    const float a = th[(int64_t)row_dpar(C, K) * V + v];
-    const float b = th[(int64_t)(row_dpar(C, K) + 1) * V + v];
+    const float a = at(row_dpar(C, K));
+    const float b = at(row_dpar(C, K) + 1);
     x.dpar = softplus_f(a);
     x.dperp = softplus_f(b);
     dv.sig_dpar = sigmoid_f(a);
@@ -638,6 +640,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
       for (int j = 0; j < VL; ++j) {
         if (valid[j] == 0.0f) continue;
         const int v = vox[j];
+        const uint32_t vrowb = (uint32_t)V * 4u, voff = (uint32_t)v * 4u;  // rows of V entries
         Derived D;
         {
           Vox<K, LD> x_again;
@@ -688,7 +691,8 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
           for (int q0 = 0; q0 < g.nbh; q0 += kNb) {
             int u[kNb];
 #pragma unroll
-            for (int e = 0; e < kNb; ++e) u[e] = q0 + e < g.nbh ? nbr[(int64_t)(q0 + e) * V + v] : -1;
+            for (int e = 0; e < kNb; ++e)
+              u[e] = q0 + e < g.nbh ? load_row_i32(row_base(nbr, q0 + e, V), vrowb, voff) : -1;
             float t[kNb][C];
 #pragma unroll
             for (int e = 0; e < kNb; ++e) load_row<C>(wrow, u[e] >= 0 ? u[e] : v, C, t[e]);
@@ -837,21 +841,19 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
             for (int q = 0; q < kAdamBatch; ++q)
               if (p0 + q < P) {
-                const int64_t i = (int64_t)(p0 + q) * V + v;
-                pp[q] = th[i];
-                m1[q] = mm[i];
-                v1[q] = vv[i];
+                pp[q] = load_row_f32(row_base(th, p0 + q, V), vrowb, voff);
+                m1[q] = load_row_f32(row_base(mm, p0 + q, V), vrowb, voff);
+                v1[q] = load_row_f32(row_base(vv, p0 + q, V), vrowb, voff);
               }
 #pragma unroll
             for (int q = 0; q < kAdamBatch; ++q)
               if (p0 + q < P) {
                 const int p = p0 + q;
                 if (!isfinite(gout[p])) bad_grad = true;
-                const int64_t i = (int64_t)p * V + v;
                 adam_one(pp[q], gout[p], m1[q], v1[q], A.b1, A.b2, A.eps, ss, ib);
-                th[i] = pp[q];
-                mm[i] = m1[q];
-                vv[i] = v1[q];
+                store_row_f32(row_base(th, p, V), vrowb, voff, pp[q]);
+                store_row_f32(row_base(mm, p, V), vrowb, voff, m1[q]);
+                store_row_f32(row_base(vv, p, V), vrowb, voff, v1[q]);
               }
             __builtin_amdgcn_sched_barrier(0);
           }
@@ -859,7 +861,7 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
           for (int p = 0; p < P; ++p) {
             if (!isfinite(gout[p])) bad_grad = true;
-            gm[(int64_t)p * V + v] = gout[p];
+            store_row_f32(row_base(gm, p, V), vrowb, voff, gout[p]);
           }
         }
         // bias-field adjoint dL/dlogB(x)
@@ -876,12 +878,12 @@ __device__ __forceinline__ void pass_item(const PassArgs& A, const float4* __res
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const int32_t step = 1 << (10 * a);
-            if (nbr[(int64_t)(2 * a + 1) * V + v] >= 0) {
+            if (load_row_i32(row_base(nbr, 2 * a + 1, V), vrowb, voff) >= 0) {
               const float dl = log_bias(g, cal, pc + step) - lb0;
               lt = fmaf(B0, fabsf(expm1f(dl)), lt);
               gt += dl > 0.0f ? -B0 : (dl < 0.0f ? B0 : 0.0f);
             }
-            if (nbr[(int64_t)(2 * a) * V + v] >= 0) {
+            if (load_row_i32(row_base(nbr, 2 * a, V), vrowb, voff) >= 0) {
               const float dl = lb0 - log_bias(g, cal, pc - step);
               gt += dl > 0.0f ? B0 : (dl < 0.0f ? -B0 : 0.0f);
             }
