@@ -299,7 +299,7 @@ def parse_launch(text):
     if not text:
         return None
     vals = [int(x) for x in text.split(",")]
-    keys = ("vox_per_lane", "n_split", "item_vox", "persistent", "max_blocks", "stagger")
+    keys = ("vox_per_lane", "n_split", "item_vox", "persistent", "max_blocks", "stagger", "concurrent")
     return dict(zip(keys, vals))
 
 
@@ -536,7 +536,7 @@ def main():
                     help="skip the prism_loss_grad-only leg (counter runs see the timed kernel only)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--launch", type=str, default="",
-                    help="vox_per_lane,n_split,item_vox[,persistent[,max_blocks[,stagger]]]")
+                    help="vox_per_lane,n_split,item_vox[,persistent[,max_blocks[,stagger[,concurrent]]]]")
     ap.add_argument("--workload", choices=("brain", "batched", "patches"), default="brain",
                     help="brain: the 743k-voxel volume (the metric's configuration); batched: 4096 "
                          "independent uneven patches in one problem, autotuned launch; patches: whole "

@@ -189,6 +189,16 @@ typedef struct {
                            where it does not apply (several groups, other shapes,
                            fewer than two rounds of blocks, or when the measurement
                            split's LDS would cost the variant a block per CU). */
+  int32_t concurrent;   /* 1 (the default): a plan of one launch per kernel variant
+                           (persistent 0) with several variants runs them on up to
+                           four streams at once -- the caller's and three the
+                           problem owns (default priority) -- forked from and
+                           joined back into the caller's stream with events, so
+                           that one variant's tail overlaps the others' work (this
+                           also records into a HIP graph); 0: one after the other
+                           on the caller's stream.  The enqueue of one call is
+                           atomic with respect to other host threads using the
+                           same problem. */
 } prism_launch;
 
 /* Launch shape of one bucket of groups: those with n_meas measurements, K

@@ -74,7 +74,7 @@ class ProblemInfo(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("vox_per_lane", ctypes.c_int32), ("n_split", ctypes.c_int32),
                 ("item_vox", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("max_blocks", ctypes.c_int32), ("stagger", ctypes.c_int32)]
+                ("max_blocks", ctypes.c_int32), ("stagger", ctypes.c_int32), ("concurrent", ctypes.c_int32)]
 
 
 class BucketLaunch(ctypes.Structure):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -55,7 +56,10 @@ struct Bucket {
   int item_begin, item_count;
   int xsplit;  // cross-wave buffer rows the launch needs
   int vpl;     // voxels per lane of the launch (1 for the persistent launch)
+  int stream;  // 0: the caller's stream; s > 0: the problem's side stream s - 1
 };
+
+constexpr int kSideStreams = 3;  // with the caller's: the four hardware queues a process gets
 
 }  // namespace
 
@@ -99,6 +103,13 @@ struct prism_problem {
   bool prof = false;
   std::vector<hipEvent_t> ev;
   mutable int ev_used = 0;
+  // concurrent variant launches (prism_launch.concurrent): side streams and the
+  // fork / join events, created by plan() when first needed
+  std::vector<hipStream_t> side;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  int n_side_used = 0;               // side streams the current plan uses
+  mutable std::mutex enqueue_mu;     // one call's fork / launches / join at a time
 
   void free_stitch() {
     (void)hipFree(d_st_g);
@@ -128,6 +139,9 @@ struct prism_problem {
     (void)hipFree(d_tri);
     free_stitch();
     for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : ev_join) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (auto st : side) (void)hipStreamDestroy(st);
   }
 };
 
@@ -306,6 +320,25 @@ int plan(prism_problem* h) {
       if (b.item_count > 0) buckets.push_back(b);
     }
   }
+  // concurrent variant launches: each launch to the stream with the least work so
+  // far, largest launch first (the caller's stream takes the first)
+  int n_side = 0;
+  if (!L.persistent && L.concurrent && buckets.size() > 1) {
+    n_side = std::min<int>(kSideStreams, (int)buckets.size() - 1);
+    std::vector<int64_t> work(buckets.size(), 0);
+    for (size_t b = 0; b < buckets.size(); ++b)
+      for (int i = buckets[b].item_begin; i < buckets[b].item_begin + buckets[b].item_count; ++i)
+        work[b] += cost(ordered[i]);
+    std::vector<size_t> order(buckets.size());
+    for (size_t b = 0; b < order.size(); ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work[a] > work[c]; });
+    std::vector<int64_t> load(n_side + 1, 0);
+    for (size_t b : order) {
+      const int st = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      buckets[b].stream = st;
+      load[st] += work[b];
+    }
+  }
   // records and first-stage reduction tiles
   std::vector<TileDev> tiles;
   int64_t rec_off = 0;
@@ -331,6 +364,20 @@ int plan(prism_problem* h) {
         tiles.push_back(t);
       }
   }
+  // the side streams and events (kept across plans; default priority)
+  while ((int)h->side.size() < n_side) {
+    hipStream_t st = nullptr;
+    hipEvent_t ej = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+      return fail(PRISM_E_ALLOC, "stream creation failed");
+    h->side.push_back(st);
+    if (hipEventCreateWithFlags(&ej, hipEventDisableTiming) != hipSuccess)
+      return fail(PRISM_E_ALLOC, "event creation failed");
+    h->ev_join.push_back(ej);
+  }
+  if (n_side > 0 && !h->ev_fork && hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return fail(PRISM_E_ALLOC, "event creation failed");
+  h->n_side_used = n_side;
   h->free_plan();
   h->max_item_nv = 0;
   for (const ItemDev& it : ordered) h->max_item_nv = std::max(h->max_item_nv, it.nv);
@@ -376,6 +423,7 @@ int check_launch(const prism_launch* L) {
     return fail(PRISM_E_INVALID, "persistent must be 0 or 1");
   if (L->max_blocks < 0) return fail(PRISM_E_INVALID, "max_blocks must be >= 0");
   if (L->stagger != 0 && L->stagger != 1) return fail(PRISM_E_INVALID, "stagger must be 0 or 1");
+  if (L->concurrent != 0 && L->concurrent != 1) return fail(PRISM_E_INVALID, "concurrent must be 0 or 1");
   return PRISM_OK;
 }
 
@@ -646,6 +694,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   h->launch.persistent = 0;
   h->launch.max_blocks = 0;
   h->launch.stagger = 1;
+  h->launch.concurrent = 1;
   hipError_t e = upload(&h->d_bval, bval);
   if (e == hipSuccess) e = upload(&h->d_bvec, bvec);
   if (e == hipSuccess) e = upload(&h->d_coords, coords);
@@ -896,21 +945,40 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     a.step_advance = nullptr;  // advanced once, by the first kernel
     if (e != hipSuccess) return hip_fail(e, "spatial-prior launch");
   }
+  // concurrent variant launches fork from the caller's stream and join it again
+  const int n_side = h->n_side_used;
+  std::unique_lock<std::mutex> lock(h->enqueue_mu, std::defer_lock);
+  if (n_side > 0) {
+    lock.lock();
+    e = hipEventRecord(h->ev_fork, s);
+    for (int i = 0; e == hipSuccess && i < n_side; ++i) e = hipStreamWaitEvent(h->side[i], h->ev_fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "stream fork");
+  }
   for (const Bucket& b : h->buckets) {
     a.item_base = b.item_begin;
     a.n_items = b.item_count;
     a.n_split = b.xsplit;
-    const bool timed = h->prof && h->ev_used + 2 <= (int)h->ev.size();
+    hipStream_t bs = b.stream > 0 ? h->side[b.stream - 1] : s;
+    // per-launch timing only for launches on the caller's stream
+    const bool timed = h->prof && bs == s && h->ev_used + 2 <= (int)h->ev.size();
     if (timed) (void)hipEventRecord(h->ev[h->ev_used], s);
     if (h->launch.persistent)
-      e = launch_pass_persistent(a, b.maxN, h->persistent_grid, counter, s);
+      e = launch_pass_persistent(a, b.maxN, h->persistent_grid, counter, bs);
     else
-      e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, b.vpl, b.maxN, s);
+      e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, b.vpl, b.maxN, bs);
     if (e != hipSuccess) return hip_fail(e, "fused-pass launch");
     if (timed) {
       (void)hipEventRecord(h->ev[h->ev_used + 1], s);
       h->ev_used += 2;
     }
+  }
+  if (n_side > 0) {
+    for (int i = 0; e == hipSuccess && i < n_side; ++i) {
+      e = hipEventRecord(h->ev_join[i], h->side[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join[i], 0);
+    }
+    if (e != hipSuccess) return hip_fail(e, "stream join");
+    lock.unlock();
   }
   ReduceArgs r{};
   r.groups = h->d_groups;

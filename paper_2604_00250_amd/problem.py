@@ -83,11 +83,13 @@ class Problem:
         except Exception:
             pass
 
-    def tune(self, vox_per_lane=1, n_split=1, item_vox=0, persistent=0, max_blocks=0, stagger=1, buckets=()):
+    def tune(self, vox_per_lane=1, n_split=1, item_vox=0, persistent=0, max_blocks=0, stagger=1, concurrent=1,
+             buckets=()):
         """Set the launch shape; `buckets` holds per-bucket overrides, dicts with
         n_meas, K, mode ("mse"/"nll" or 0/1), learn_diffusivity, vox_per_lane,
         n_split and item_vox."""
-        base = L.Launch(vox_per_lane, n_split, item_vox, int(persistent), int(max_blocks), int(stagger))
+        base = L.Launch(vox_per_lane, n_split, item_vox, int(persistent), int(max_blocks), int(stagger),
+                        int(concurrent))
         arr = (L.BucketLaunch * max(len(buckets), 1))()
         for i, b in enumerate(buckets):
             mode = b["mode"]
@@ -100,7 +102,8 @@ class Problem:
         ln = L.Launch()
         L.check(L.lib().prism_problem_launch(self.handle, ctypes.byref(ln)))
         return dict(vox_per_lane=ln.vox_per_lane, n_split=ln.n_split, item_vox=ln.item_vox,
-                    persistent=ln.persistent, max_blocks=ln.max_blocks, stagger=ln.stagger)
+                    persistent=ln.persistent, max_blocks=ln.max_blocks, stagger=ln.stagger,
+                    concurrent=ln.concurrent)
 
     def buckets(self) -> list:
         """The problem's (N, K, mode, learned D) buckets with the shape each runs with."""

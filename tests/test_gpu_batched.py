@@ -43,6 +43,32 @@ def test_batched_groups_match_oracle(launch):
     _all_groups_match(w, r, "batched")
 
 
+def test_concurrent_variant_launches_are_bitwise_the_serial_ones():
+    """A per-variant plan with several variants runs them on up to four
+    streams (forked from and joined back into the caller's); each item writes
+    its own record and the reductions follow the join, so the results equal
+    those of the same plan launched one variant after another, bit for bit,
+    and stay so over several fused Adam iterations."""
+    import torch
+    from paper_2604_00250_amd.problem import DeviceState, Problem
+    w = _workload()
+    shape = dict(vox_per_lane=1, n_split=0, item_vox=0, persistent=0)
+    states = []
+    for conc in (1, 0):
+        prob = Problem(w.groups, launch=dict(shape, concurrent=conc))
+        st = DeviceState(prob, ys=[g.y for g in w.groups], thetas=[g.theta for g in w.groups])
+        for _ in range(3):
+            st.iteration(1e-2)
+        st.loss_grad()
+        torch.cuda.synchronize()
+        states.append(st)
+        say(f"[concurrent={conc}] launch {prob.launch()} plan {prob.plan_info()} buckets {len(prob.buckets())}")
+    a, b = states
+    assert a.prob.plan_info()["launches"] >= 4
+    for k in ("params", "m", "v", "grad", "loss", "step", "status"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+
+
 def test_persistent_blocks_run_several_items_each():
     """max_blocks caps the persistent grid far below the item count, so every
     block pops and runs many items in turn (LDS reuse across items of different
