@@ -59,11 +59,12 @@ ALG_VALU_PER_PAIR = 84
 #     weighted adds into S 2 (8K)                                     -> 8K + 3
 #   data term: beta - y 1, residual (gain S + (beta - y)) 1, squared-residual
 #     accumulate 1                                                      -> 3
-#   adjoint: seed S 1 (the alpha_n sum's input), dS 1, dS(-2b) 1, isotropic 3;
-#     per fibre the sums of dS e1 and dS e12 2, a2 e12 1, a1 e1 + a2 e12 1,
-#     cos dS(-2b) 1, times that 1, direction 3 (9K)                     -> 9K + 6
-#   total 17K + 12 = 63 VALU and 2K = 6 exps; reported as frac_min_count.
-MIN_VALU_PER_PAIR = 63
+#   adjoint: seed S 1 (the alpha_n sum's input), dS 1, dS(-2b) 1, the two
+#     direction factors times dS(-2b) 2, isotropic 3; per fibre the sums of
+#     dS e1 and dS e12 2, a2 e12 1, a1 e1 + a2 e12 1, times cos 1,
+#     direction 3 (8K)                                                  -> 8K + 8
+#   total 16K + 14 = 62 VALU and 2K = 6 exps at K = 3; reported as frac_min_count.
+MIN_VALU_PER_PAIR = 62
 ALG_EXP_PER_PAIR = 6
 # At b = 0 every attenuation is exactly 1 and the kernel runs whole 16-measurement
 # tiles of an acquisition's leading b = 0 measurements with the data term and the

@@ -322,6 +322,10 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of compartment c's signal
   const float dS = seed * c.x;
   const float dSz = dS * c.z;             // dS (-2b), the factor of dE/dcos shared by the fibres
+  // from three fibres on, fold dS (-2b) into the two per-voxel factors once per pair
+  // (two products) rather than into each fibre's cosine (one product per fibre)
+  constexpr bool kFold = K >= 3;
+  const float a1z = kFold ? x.a1 * dSz : x.a1, a2z = kFold ? x.a2 * dSz : x.a2;
   acc.r[0] = fmaf(dS, b.y, acc.r[0]);
   acc.r[1] = fmaf(dS, b.z, acc.r[1]);
   acc.r[2] = fmaf(dS, b.w, acc.r[2]);
@@ -329,10 +333,9 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   for (int k = 0; k < K; ++k) {
     acc.r[AC::kE1 + k] = fmaf(dS, e1[k], acc.r[AC::kE1 + k]);
     acc.r[AC::kE12 + k] = fmaf(dS, e12[k], acc.r[AC::kE12 + k]);
-    // dE/dcos = -2b cos (Dpar f_in e1 + (Dpar - Dperp)(1 - f_in) e12); the fibre's
-    // F_k multiplies the sums once per voxel, after the loop
-    const float t = fmaf(x.a1, e1[k], x.a2 * e12[k]);
-    const float dc = (cc[k] * dSz) * t;
+    // dE/dcos = -2b cos (Dpar f_in e1 + (Dpar - Dperp)(1 - f_in) e12), here times dS;
+    // the fibre's F_k multiplies the sums once per voxel, after the loop
+    const float dc = (kFold ? cc[k] : cc[k] * dSz) * fmaf(a1z, e1[k], a2z * e12[k]);
     acc.r[AC::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[AC::kGd + 3 * k + 0]);
     acc.r[AC::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[AC::kGd + 3 * k + 1]);
     acc.r[AC::kGd + 3 * k + 2] = fmaf(dc, gz, acc.r[AC::kGd + 3 * k + 2]);
