@@ -8,8 +8,8 @@ The kernels need, for z >= 0,
 Small arguments, z < 3.75, are evaluated in float64 (on CDNA3/4 a float64
 FMA issues at the rate of a float32 one) from two even functions of t = z^2,
 fitted here as Chebyshev series in x = 2 t / 3.75^2 - 1 and stored as
-polynomials in x (Horner: one float64 FMA per degree; the coefficients stay
-below 0.3 in magnitude, so the conversion is well conditioned):
+polynomials in x (evaluated by Estrin's scheme in float64; the coefficients
+stay below 0.3 in magnitude, so the conversion is well conditioned):
     G(t)   = log I0(z) / t      ->  log I0e(z) = t G(t) - z
     rho(t) = R(z) / z           ->  1 - R(z)   = 1 - z rho(t)
 each result rounded to float32 once.
@@ -155,6 +155,23 @@ def _horner64(p, x):
     return acc
 
 
+def _estrin64(p, x):
+    """Estrin's scheme in float64, in the kernels' order: pairs with x, then
+    pairs of pairs with x^2, x^4, x^8."""
+    p = [np.float64(a) for a in p]
+    x2 = x * x
+    x4 = x2 * x2
+    x8 = x4 * x4
+    lvl = [p[2 * i + 1] * x + p[2 * i] if 2 * i + 1 < len(p) else np.full_like(x, p[2 * i])
+           for i in range((len(p) + 1) // 2)]
+    for xp in (x2, x4, x8):
+        if len(lvl) == 1:
+            break
+        lvl = [lvl[2 * i + 1] * xp + lvl[2 * i] if 2 * i + 1 < len(lvl) else lvl[2 * i]
+               for i in range((len(lvl) + 1) // 2)]
+    return lvl[0]
+
+
 def _clenshaw64(c, x):
     x2 = x + x
     b1 = np.zeros_like(x)
@@ -176,8 +193,8 @@ def evaluate_f32(z, coefs=None):
     zd = z[s].astype(np.float64)
     t = zd * zd
     x = t * (2.0 / Z_SPLIT ** 2) - 1.0
-    G = _horner64(np.asarray(cG, np.float64), x)
-    rho = _horner64(np.asarray(cR, np.float64), x)
+    G = _estrin64(np.asarray(cG, np.float64), x)
+    rho = _estrin64(np.asarray(cR, np.float64), x)
     w = 1.0 - zd * rho
     omr[s] = w.astype(f32)
     q[s] = (2.0 * zd * w).astype(f32)

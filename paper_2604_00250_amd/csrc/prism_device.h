@@ -179,20 +179,31 @@ __device__ __forceinline__ float horner(const float (&c)[N], float x) {
   return acc;
 }
 
-// Horner's rule in float64 over a table in constant memory (the small-argument
-// branch).  `c` is read where the branch runs: the table offset passes
-// through an empty asm statement there, so the compiler cannot hoist the 2N
-// scalar registers of the coefficients out of the measurement loop (float64
-// operands cannot be instruction literals on this architecture).
+// Float64 polynomials over a table in constant memory (the small-argument
+// branch).  `c` is read where the branch runs: the table offset passes through
+// an empty asm statement there, so the compiler cannot hoist the 2N scalar
+// registers of the coefficients out of the measurement loop (float64 operands
+// cannot be instruction literals on this architecture).  Evaluated by Estrin's
+// scheme: coefficient pairs, then pairs of pairs with x^2, then with x^4 and
+// x^8 (the powers shared by the two small-argument polynomials), so the
+// longest chain of dependent float64 operations is about five instead of
+// N - 1: this branch runs for a few lanes of most waves, and its latency, not
+// its work, is what the measurement loop waits on.
 template <int N>
-__device__ __forceinline__ double horner_d(const double* c, double x) {
+__device__ __forceinline__ double estrin_d(const double* c, double x, double x2, double x4, double x8) {
+  static_assert(N >= 2 && N <= 16, "Estrin evaluation of degree 1..15");
   int off = 0;
   asm volatile("" : "+s"(off));
   c += off;
-  double acc = c[N - 1];
+  constexpr int N1 = (N + 1) / 2, N2 = (N1 + 1) / 2, N3 = (N2 + 1) / 2;
+  double p1[N1], p2[N2], p3[N3];
 #pragma unroll
-  for (int i = N - 2; i >= 0; --i) acc = fma(acc, x, c[i]);
-  return acc;
+  for (int i = 0; i < N1; ++i) p1[i] = 2 * i + 1 < N ? fma(c[2 * i + 1], x, c[2 * i]) : c[2 * i];
+#pragma unroll
+  for (int i = 0; i < N2; ++i) p2[i] = 2 * i + 1 < N1 ? fma(p1[2 * i + 1], x2, p1[2 * i]) : p1[2 * i];
+#pragma unroll
+  for (int i = 0; i < N3; ++i) p3[i] = 2 * i + 1 < N2 ? fma(p2[2 * i + 1], x4, p2[2 * i]) : p2[2 * i];
+  return N3 == 1 ? p3[0] : fma(p3[1], x8, p3[0]);
 }
 
 // Eq. 9 terms for z >= 0: returns log I0e(z) = log I0(z) - z and writes
@@ -200,7 +211,8 @@ __device__ __forceinline__ double horner_d(const double* c, double x) {
 // 1.3e-7 relative of the exact value over [0, 1e5] (host emulation of this
 // algorithm; the tests measure the device).
 //   z < 3.75: float64 polynomials in t = z^2 (log I0(z) = t G(t),
-//             R(z) = z rho(t)), one rounding to float32 per result;
+//             R(z) = z rho(t)), by Estrin's scheme, one rounding to float32
+//             per result;
 //   z >= 3.75: float32 rational functions u P(x)/Q(x), x = 2u - 1, u = 3.75/z,
 //             of l = log(sqrt(2 pi z) I0e(z)) and d = q - 1 (for z > 2000 d is
 //             w/4 + w^2/4 + 25w^3/64, w = 1/z), so that
@@ -212,8 +224,11 @@ __device__ __forceinline__ float log_i0e(float z, float& omr, float& q) {
     // the two polynomials one after the other (one float64 accumulator live)
     const double zd = (double)z;
     const double x = fma(zd * zd, 2.0 / ((double)kBesselSplit * (double)kBesselSplit), -1.0);
-    const float li = (float)fma(zd * zd, horner_d<PRISM_SMALL_G_N>(kSmallG, x), -zd);
-    const double w = fma(-zd, horner_d<PRISM_SMALL_RHO_N>(kSmallRho, x), 1.0);
+    const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
+    static_assert(PRISM_SMALL_G_N <= 16 && PRISM_SMALL_RHO_N <= 16 && PRISM_SMALL_G_N > 8 &&
+                  PRISM_SMALL_RHO_N > 8, "Estrin levels for the small-argument degrees");
+    const float li = (float)fma(zd * zd, estrin_d<PRISM_SMALL_G_N>(kSmallG, x, x2, x4, x8), -zd);
+    const double w = fma(-zd, estrin_d<PRISM_SMALL_RHO_N>(kSmallRho, x, x2, x4, x8), 1.0);
     omr = (float)w;
     q = (float)(2.0 * zd * w);
     return li;

@@ -153,7 +153,21 @@ def test_autotuner_picks_valid_shapes_per_bucket_and_caches_them(tmp_path):
     assert torch.equal(st.params, p0) and int(st.step[0].item()) == 0
     st.loss_grad()
     torch.cuda.synchronize()
-    assert np.allclose(st.loss_host(), ref, rtol=1e-6, atol=0)
+    # a different plan sums the same terms in a different order: equal to rounding
+    # of the summed parts.  An NLL data term is a float32-summed positive part plus
+    # the constant 2 sigma_log N |M|, which nearly cancel on some small patches, so
+    # the tolerance scales with the parts, not with their sum.
+    got = st.loss_host()
+    scale = np.abs(ref).copy()
+    for i, g in enumerate(w.groups):
+        if g.mode == "nll":
+            c = abs(2.0 * float(g.theta["sigma_log"]) * g.acq.n * g.n_vox)
+            scale[i, 0] += c
+            scale[i, 9] += c
+    rel = np.abs(got - ref) / np.maximum(scale, 1e-30)
+    worst = np.unravel_index(np.argmax(rel), rel.shape)
+    say(f"[tune] loss after re-planning: worst relative change {rel.max():.2e} at group {worst[0]} term {worst[1]}")
+    assert rel.max() <= 1e-6
     res2 = autotune(st, cache=cache)
     assert res2["cached"] and res2["launch"] == res["launch"]
     key = lambda b: (b["n_meas"], b["K"], b["mode"])  # noqa: E731
