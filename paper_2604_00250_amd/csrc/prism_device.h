@@ -102,6 +102,63 @@ __device__ __forceinline__ float row_shr1_zero(float x) {
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x111, 0xf, 0xf, true));
 }
 
+// Per-measurement sums over each row of 16 lanes, fed one value per lane per
+// measurement in groups of four (measurement t = 4g + u of a tile of 16):
+// afterwards lane l of a row holds the row's sum for measurement
+// row_scatter_index(l).  Within a group the four values are reduce-scattered
+// over each quad of lanes: the pair (u, u + 1) and then the two pair sums are
+// combined as keep + partner(send), (keep, send) = (later, earlier) where the
+// lane's level bit is set and (earlier, later) where it is clear, with the
+// partner lane xor 1, then xor 2, and the level bits b0^b2, b1^b2 (b = the
+// lane's bits in the row), which differ between partners, so each quad lane
+// ends with the quad's sum for one of the group's measurements.  The level
+// bits also agree between lanes l and l^7 and between l and l^15, so adding
+// the half-row mirror and then the row mirror sums the four quads of the row
+// measurement by measurement; bank g (lanes 4g..4g+3) of the row keeps the
+// result of group g.  Per group of four measurements: three combines of three
+// VALU operations, two adds with a mirrored operand and one select (a
+// matrix-core one-hot accumulation takes one v_mfma_f32_16x16x4f32 per
+// measurement, which holds the SIMD for its 32 cycles).
+struct RowScatter {
+  float x0, r1, q;  // within a group: pending value, pending pair sum, the quad result
+  float acc;        // bank g of the row: the row sums of group g's measurements
+};
+struct RowScatterMasks {
+  bool m[2];        // per lane: the level bits b0^b2, b1^b2
+};
+__device__ __forceinline__ RowScatterMasks row_scatter_masks(int lane) {
+  const uint32_t l = (uint32_t)lane & 15u;
+  const uint32_t b0 = l & 1u, b1 = (l >> 1) & 1u, b2 = (l >> 2) & 1u;
+  return {{(b0 ^ b2) != 0, (b1 ^ b2) != 0}};
+}
+// the measurement of the tile (0..15) whose row sum lane l holds at the end
+__device__ __forceinline__ int row_scatter_index(int lane) {
+  const int l = lane & 15, b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1;
+  return (l & 12) | (b0 ^ b2) | (b1 ^ b2) << 1;
+}
+template <int CTRL>
+__device__ __forceinline__ float row_scatter_combine(float x, float y, bool m) {
+  return (m ? y : x) + dpp_f32<CTRL>(m ? x : y);
+}
+// measurement u (0..3, known at compile time) of the current group
+__device__ __forceinline__ void row_scatter_push(RowScatter& s, float v, int u, const RowScatterMasks& M) {
+  if ((u & 1) == 0) {
+    s.x0 = v;
+    return;
+  }
+  const float r = row_scatter_combine<0xB1>(s.x0, v, M.m[0]);   // quad_perm [1,0,3,2]
+  if (u == 1)
+    s.r1 = r;
+  else
+    s.q = row_scatter_combine<0x4E>(s.r1, r, M.m[1]);           // quad_perm [2,3,0,1]
+}
+// end of group g: here = (lane's bank in the row == g)
+__device__ __forceinline__ void row_scatter_group(RowScatter& s, bool here) {
+  float t = s.q + dpp_f32<0x141>(s.q);  // row_half_mirror: lane xor 7
+  t += dpp_f32<0x140>(t);               // row_mirror: lane xor 15
+  s.acc = here ? t : s.acc;
+}
+
 // Sum over the 64 lanes of a wave; the total lands in lane 63 (other lanes hold
 // partial sums).  quad_perm xor 1, xor 2, half-row mirror, row mirror, then
 // the two row broadcasts that chain rows 0-3.

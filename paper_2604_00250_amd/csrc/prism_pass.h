@@ -350,19 +350,17 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   }
 }
 
-typedef float v4f __attribute__((ext_vector_type(4)));
+static_assert(kTile == 16 && kPf == 4, "the per-measurement sums take a tile of 16 over a row of 16 lanes, 4 at a time");
 
 // Measurements [nb, ne) for the VL voxels of this lane, in tiles of kTile.
 // The per-measurement sums over the wave's 64 x VL voxels (the beta_n adjoint,
 // and the alpha_n adjoint divided by exp(alpha_n), which multiplies the tile's
-// totals) are accumulated on the matrix core: with A = this lane's
-// partial and B = the one-hot column t = n - n0, v_mfma_f32_16x16x4f32 adds
-// each lane's value into column t of a 16x16 tile; after the tile, lane l
-// holds rows 4(l/16)..4(l/16)+3 of column l%16, so four adds and two lane
-// exchanges give the wave total for measurement n0 + l%16.  Invalid lanes
-// (beyond the item) carry valid = 0, which removes them from every sum.
-// FULL: every lane's voxels are in the item (the validity factors are 1 and
-// drop out at compile time).
+// totals) are reduced over each row of 16 lanes as the measurements arrive
+// (RowScatter, four at a time); after the tile lane l holds its row's sum for
+// measurement n0 + row_scatter_index(l), and two lane exchanges (xor 16,
+// xor 32) add the four rows.  Invalid lanes (beyond the item) carry valid = 0,
+// which removes them from every sum.  FULL: every lane's voxels are in the
+// item (the validity factors are 1 and drop out at compile time).
 template <int K, int MODE, bool LD, int VL, bool FULL>
 __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<K, LD> (&acc)[VL],
                                                  const float* yg, int64_t V, const int (&vox)[VL],
@@ -370,7 +368,6 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
                                                  const float4* __restrict__ acq,
                                                  int nb, int ne, int nb0, int N, float inv_s2, int lane,
                                                  float* wacc, double& dloss, double& dsig) {
-  const int lane16 = lane & 15;
   uint32_t voff[VL];  // byte offsets of the lane's voxels in a row of y
 #pragma unroll
   for (int j = 0; j < VL; ++j) voff[j] = (uint32_t)vox[j] * 4u;
@@ -381,14 +378,15 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
   for (int u = 0; u < kPf; ++u)
 #pragma unroll
     for (int j = 0; j < VL; ++j) yr[u][j] = load_row_f32(yg + (int64_t)min(nb + u, ne - 1) * V, rowb, voff[j]);
-  v4f Da, Db;
+  const RowScatterMasks sm = row_scatter_masks(lane);
+  const int bank = (lane >> 2) & 3;   // the group of four measurements this lane's row sums keep
+  RowScatter sa, sb;                  // the alpha and beta sums of the tile
   float lacc, sacc;
-  float sel;  // one-hot over the 16 lanes of a row: 1 at lane16 == t (column t of the tile)
   int n0 = nb;
-  // one measurement: the ring slot u is refilled (measurement n + kPf) only after
-  // its value has been consumed, so the load can target the slot's register
-  // directly and the wait for it lands kPf measurements later
-  auto body = [&](int t, float (&slot)[VL]) {
+  // one measurement, u = n - n0 mod 4: the ring slot u is refilled (measurement
+  // n + kPf) only after its value has been consumed, so the load can target the
+  // slot's register directly and the wait for it lands kPf measurements later
+  auto body = [&](int t, int u, float (&slot)[VL]) {
     const int n = n0 + t;
     const float4 a = acq[3 * n + 0];
     const float4 b = acq[3 * n + 1];
@@ -407,20 +405,28 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     const float* row = yg + (int64_t)min(n + kPf, ne - 1) * V;  // clamped: in bounds
 #pragma unroll
     for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
-    Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
-    Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    sel = row_shr1_zero(sel);  // moves the one to lane16 == t + 1
+    row_scatter_push(sa, pa, u, sm);
+    row_scatter_push(sb, pb, u, sm);
+  };
+  // a measurement past the end of the range: zeros complete the group
+  auto body_none = [&](int u) {
+    row_scatter_push(sa, 0.0f, u, sm);
+    row_scatter_push(sb, 0.0f, u, sm);
+  };
+  auto group_end = [&](int t0) {
+    const bool here = bank == (t0 >> 2);
+    row_scatter_group(sa, here);
+    row_scatter_group(sb, here);
   };
   auto tile_begin = [&]() {
-    Da = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    Db = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     lacc = 0.0f;
     sacc = 0.0f;
-    sel = lane16 == 0 ? 1.0f : 0.0f;
+    sa.acc = 0.0f;
+    sb.acc = 0.0f;
   };
   // the same at b = 0 (see pair_b0)
   float Fsum[VL], dS0[VL];
-  auto body_b0 = [&](int t, float (&slot)[VL]) {
+  auto body_b0 = [&](int t, int u, float (&slot)[VL]) {
     const int n = n0 + t;
     const float4 c = acq[3 * n + 2];
     float pa = 0.0f, pb = 0.0f;
@@ -436,30 +442,30 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     const float* row = yg + (int64_t)min(n + kPf, ne - 1) * V;  // clamped: in bounds
 #pragma unroll
     for (int j = 0; j < VL; ++j) slot[j] = load_row_f32(row, rowb, voff[j]);
-    Da = __builtin_amdgcn_mfma_f32_16x16x4f32(pa, sel, Da, 0, 0, 0);
-    Db = __builtin_amdgcn_mfma_f32_16x16x4f32(pb, sel, Db, 0, 0, 0);
-    sel = row_shr1_zero(sel);
+    row_scatter_push(sa, pa, u, sm);
+    row_scatter_push(sb, pb, u, sm);
   };
-  // four straight-line measurements (MSE; NLL branches inside its Bessel terms)
+  // four straight-line measurements from t0 (a multiple of kPf)
   auto group = [&](int t0) {
 #pragma unroll
     for (int u = 0; u < kPf; ++u) {
-      body(t0 + u, yr[u]);
+      body(t0 + u, u, yr[u]);
       if ((u + 1) % sched_span(K, MODE, LD, VL) == 0) __builtin_amdgcn_sched_barrier(0);
     }
+    group_end(t0);
   };
-  // wave totals of the tile's per-measurement sums: lane l of the accumulator
-  // tile holds rows 4(l/16).. of column l%16
+  // wave totals of the tile's per-measurement sums (cnt measurements)
   auto tile_end = [&](int cnt) {
-    float ra = (Da[0] + Da[1]) + (Da[2] + Da[3]);
-    float rb = (Db[0] + Db[1]) + (Db[2] + Db[3]);
+    float ra = sa.acc, rb = sb.acc;
     ra += xor16_f32(ra);
     rb += xor16_f32(rb);
     ra += xor32_f32(ra);
     rb += xor32_f32(rb);
-    if (lane < cnt) {
-      wacc[n0 + lane] = fmaf(ra, acq[3 * (n0 + lane) + 2].x, wacc[n0 + lane]);  // times exp(alpha_n)
-      wacc[N + n0 + lane] += rb;
+    const int tn = row_scatter_index(lane);
+    if (lane < kTile && tn < cnt) {
+      const int n = n0 + tn;
+      wacc[n] = fmaf(ra, acq[3 * n + 2].x, wacc[n]);  // times exp(alpha_n)
+      wacc[N + n] += rb;
     }
     dloss += (double)lacc;
     if (MODE == kNLL) dsig += (double)sacc;  // 0 for MSE
@@ -482,7 +488,8 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
 #pragma unroll 1
       for (int t0 = 0; t0 < kTile; t0 += kPf) {
 #pragma unroll
-        for (int u = 0; u < kPf; ++u) body_b0(t0 + u, yr[u]);
+        for (int u = 0; u < kPf; ++u) body_b0(t0 + u, u, yr[u]);
+        group_end(t0);
         __builtin_amdgcn_sched_barrier(0);
       }
       tile_end(kTile);
@@ -503,13 +510,20 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
     }
     if (n0 < ne) {  // the range's last, partial tile
       const int cnt = ne - n0;
-      const int full = cnt - cnt % kPf;
+      const int full = cnt & ~(kPf - 1);  // cnt > 0
       tile_begin();
 #pragma unroll 1
       for (int t0 = 0; t0 < full; t0 += kPf) group(t0);
+      if (full < cnt) {
 #pragma unroll
-      for (int u = 0; u + 1 < kPf; ++u)
-        if (full + u < cnt) body(full + u, yr[u]);
+        for (int u = 0; u < kPf; ++u) {
+          if (full + u < cnt)
+            body(full + u, u, yr[u]);
+          else
+            body_none(u);
+        }
+        group_end(full);
+      }
       tile_end(cnt);
     }
   } else {
@@ -518,8 +532,13 @@ __device__ __forceinline__ void measurement_loop(const Vox<K, LD> (&x)[VL], Acc<
       tile_begin();
       for (int t0 = 0; t0 < cnt; t0 += kPf) {
 #pragma unroll
-        for (int u = 0; u < kPf; ++u)
-          if (t0 + u < cnt) body(t0 + u, yr[u]);
+        for (int u = 0; u < kPf; ++u) {
+          if (t0 + u < cnt)
+            body(t0 + u, u, yr[u]);
+          else
+            body_none(u);
+        }
+        group_end(t0);
       }
       tile_end(cnt);
     }
