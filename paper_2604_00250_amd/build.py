@@ -4,10 +4,7 @@
 
 Every HIP translation unit is compiled with packed-FP32 instructions turned
 off (``-target-feature -packed-fp32-ops``): the kernels are written for
-scalar FP32 issue.  Matrix-core accumulators are kept in ordinary VGPRs
-(``-amdgpu-mfma-vgpr-form``): the fused pass uses the matrix core only as a
-reduction engine, and the accumulation-register form made the compiler
-shuffle the accumulators between registers on every measurement group.
+scalar FP32 issue.
 """
 import os
 import shutil
@@ -52,7 +49,6 @@ def build(verbose: bool = False) -> str:
     flags = [f"-DPRISM_SOURCE_HASH=\"{source_hash()}\"",
              "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(HERE, "..", "include")]
     for src, obj_name, extra in SOURCES:
         obj = os.path.join(CSRC, obj_name)

@@ -13,9 +13,6 @@ namespace prism {
 #ifndef PRISM_PASS_MIN_WAVES
 #define PRISM_PASS_MIN_WAVES 1
 #endif
-#ifndef PRISM_TILE
-#define PRISM_TILE 16
-#endif
 #ifndef PRISM_PERSISTENT_MIN_WAVES
 #define PRISM_PERSISTENT_MIN_WAVES 2
 #endif
@@ -25,8 +22,8 @@ namespace prism {
 #ifndef PRISM_FOUR_WAVES
 #define PRISM_FOUR_WAVES 1
 #endif
-// measurements per matrix-core reduction tile (8 or 16 columns of the 16x16 tile)
-constexpr int kTile = PRISM_TILE;
+// measurements per tile of the per-measurement sums (one per lane of a row of 16)
+constexpr int kTile = 16;
 // depth of the y prefetch ring (measurements ahead); kTile is a multiple of it
 constexpr int kPf = PRISM_PREFETCH;
 static_assert(kTile % kPf == 0, "tile must be a multiple of the prefetch depth");
@@ -350,7 +347,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   }
 }
 
-static_assert(kTile == 16 && kPf == 4, "the per-measurement sums take a tile of 16 over a row of 16 lanes, 4 at a time");
+static_assert(kPf == 4, "the per-measurement sums take four measurements at a time");
 
 // Measurements [nb, ne) for the VL voxels of this lane, in tiles of kTile.
 // The per-measurement sums over the wave's 64 x VL voxels (the beta_n adjoint,
