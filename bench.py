@@ -54,17 +54,19 @@ ALG_VALU_PER_PAIR = 84
 # bias field, each fibre's fraction and f_intra applied once per voxel; a fibre's
 # attenuation taken as f_in e1 + (1 - f_in) e12 with e1 and e12 = e1 e2 one exp
 # each, so that e2 is never formed and the f_intra and log-bias adjoints follow
-# per voxel from the per-fibre sums of dS e1 and dS e12):
-#   forward: mixture start 3; per fibre g.d 3, cos^2 1, two exponents 2, two
-#     weighted adds into S 2 (8K)                                     -> 8K + 3
+# per voxel from the per-fibre sums of dS e1 and dS e12; with fixed
+# diffusivities the staged gradient direction carries sqrt(b Dpar log2 e), so
+# that e1 = exp2(-cs^2) with cs the scaled cosine, and the adjoint's constant
+# -2 ln 2 / Dpar sits in the per-voxel direction factors):
+#   forward: mixture start 3; per fibre scaled cosine 3, its square 1, the e12
+#     exponent 1, two weighted adds into S 2 (7K)                     -> 7K + 3
 #   data term: beta - y 1, residual (gain S + (beta - y)) 1, squared-residual
 #     accumulate 1                                                      -> 3
-#   adjoint: seed S 1 (the alpha_n sum's input), dS 1, dS(-2b) 1, the two
-#     direction factors times dS(-2b) 2, isotropic 3; per fibre the sums of
-#     dS e1 and dS e12 2, a2 e12 1, a1 e1 + a2 e12 1, times cos 1,
-#     direction 3 (8K)                                                  -> 8K + 8
-#   total 16K + 14 = 62 VALU and 2K = 6 exps at K = 3; reported as frac_min_count.
-MIN_VALU_PER_PAIR = 62
+#   adjoint: seed S 1 (the alpha_n sum's input), dS 1, the two direction
+#     factors times dS 2, isotropic 3; per fibre the sums of dS e1 and dS e12 2,
+#     a2 e12 1, a1 e1 + a2 e12 1, times cs 1, direction 3 (8K)          -> 8K + 7
+#   total 15K + 13 = 58 VALU and 2K = 6 exps at K = 3; reported as frac_min_count.
+MIN_VALU_PER_PAIR = 58
 ALG_EXP_PER_PAIR = 6
 # At b = 0 every attenuation is exactly 1 and the kernel runs whole 16-measurement
 # tiles of an acquisition's leading b = 0 measurements with the data term and the

@@ -131,7 +131,10 @@ typedef struct {
  * with tau 0.15, lam_orphan 0.01, lam_cont 0.005, lam_order 0.01 (Sec. 2.4),
  * and values the paper does not print (readings): the calibration L2 weights
  * 0.01, lam_tv 0.01, and s0_orphan 0.1 (S0 below which WM is penalised, on
- * b0-normalised signals).  All must be finite and >= 0; s0_orphan > 0. */
+ * b0-normalised signals).  All must be finite and >= 0; s0_orphan > 0 and
+ * d_par > 0 (a stick with no parallel diffusivity is not a fibre; it is also
+ * the unit of the fibre attenuation's exponent in the fused pass), else
+ * PRISM_E_INVALID. */
 typedef struct {
   float d_csf, d_gm, d_res, d_par, d_perp;
   float lam_sp, huber_delta, lam_rep, lam_sparse, tau_sparse;

@@ -494,6 +494,7 @@ int32_t prism_problem_create(prism_problem** out, const prism_group_desc* groups
   for (float x : mv)
     if (!std::isfinite(x) || x < 0.0f) return fail(PRISM_E_INVALID, "model constants must be finite and >= 0");
   if (!(model->s0_orphan > 0.0f)) return fail(PRISM_E_INVALID, "s0_orphan must be > 0");
+  if (!(model->d_par > 0.0f)) return fail(PRISM_E_INVALID, "d_par must be > 0");
   // acquisitions
   std::vector<int32_t> acq_off(n_acq);
   std::vector<float> bval, bvec;

@@ -49,27 +49,33 @@ constexpr int sched_span(int K, int MODE, bool LD, int VL) {
 }
 
 // ---------------------------------------------------------------------------
-// staging of one measurement: 3 x float4
-//   a = (gx, gy, gz, kpar)   kpar  = -b Dpar log2(e)   (Dpar = 1 with learned D)
-//   b = (kperp, Ecsf, Egm, Eres)                          Eq. 4
-//   c = (exp(alpha_n), beta_n, -2 b, kpar - kperp)        gain, offset, adjoint factor,
-//                                                         and the cos^2 coefficient of
-//                                                         log2(e1 e2) (0 with learned D)
+// staging of one measurement: 3 x float4.  With fixed diffusivities:
+//   a = (s gx, s gy, s gz, kpar)   s = sqrt(b Dpar log2(e)), kpar = -b Dpar log2(e)
+//   b = (kperp, Ecsf, Egm, Eres)   kperp = -b Dperp log2(e); the balls' Eq. 4
+//   c = (exp(alpha_n), beta_n, Dperp/Dpar - 1, 0)
+// so that with cs = (s g).d = s cos the fibre terms are e1 = exp2(-cs^2) and
+// e12 = exp2(kperp + (Dperp/Dpar - 1) cs^2), and d cs / d d = s g is the
+// staged vector itself.  With learned diffusivities (Dpar, Dperp per voxel):
+//   a = (gx, gy, gz, -b log2(e)), b = (-b log2(e), Ecsf, Egm, Eres),
+//   c = (exp(alpha_n), beta_n, -2 b, 0)
+// (the fourth component of a and of c is not read with fixed diffusivities: the
+// three read share one LDS load)
 // ---------------------------------------------------------------------------
 inline __device__ void stage_acquisition(const PassArgs& A, const GroupDev& g, float4* acq) {
   const float* cal = A.th_cal + g.cal_off;
   const float* alpha = cal + g.n_bias;
   const float* beta = alpha + g.N;
-  const float dpar = g.learn_d ? 1.0f : A.model.d_par;
+  const float dpar = g.learn_d ? 1.0f : A.model.d_par;     // d_par > 0 (checked at create)
   const float dperp = g.learn_d ? 1.0f : A.model.d_perp;
   for (int n = threadIdx.x; n < g.N; n += blockDim.x) {
     const float b = A.bval[g.acq_off + n];
     const float* gv = A.bvec + 3 * (int64_t)(g.acq_off + n);
-    acq[3 * n + 0] = make_float4(gv[0], gv[1], gv[2], -b * dpar * kLog2e);
-    acq[3 * n + 1] = make_float4(-b * dperp * kLog2e, expf(-b * A.model.d_csf),
-                                 expf(-b * A.model.d_gm), expf(-b * A.model.d_res));
     const float kpar = -b * dpar * kLog2e, kperp = -b * dperp * kLog2e;
-    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], -2.0f * b, g.learn_d ? 0.0f : kpar - kperp);
+    const float s = g.learn_d ? 1.0f : sqrtf(-kpar);
+    acq[3 * n + 0] = make_float4(s * gv[0], s * gv[1], s * gv[2], kpar);
+    acq[3 * n + 1] = make_float4(kperp, expf(-b * A.model.d_csf), expf(-b * A.model.d_gm),
+                                 expf(-b * A.model.d_res));
+    acq[3 * n + 2] = make_float4(expf(alpha[n]), beta[n], g.learn_d ? -2.0f * b : dperp / dpar - 1.0f, 0.0f);
   }
 }
 
@@ -86,7 +92,8 @@ struct Vox {
   float Fa[K];      // B S0 f_k f_in:       weight of e1
   float Fb[K];      // B S0 f_k (1 - f_in): weight of e12
   float d[K][3];    // unit directions
-  float a1, a2;     // Dpar f_in, (Dpar - Dperp)(1 - f_in): dE/dcos = -2b cos (a1 e1 + a2 e12)
+  float a1, a2;     // learned D: Dpar f_in, (Dpar - Dperp)(1 - f_in), dE/dcos = -2b cos (a1 e1 + a2 e12);
+                    // fixed D: -2 ln2 f_in, -2 ln2 (1 - Dperp/Dpar)(1 - f_in), dE/dcs = cs (a1 e1 + a2 e12)
   float dpar, dperp;
 };
 
@@ -244,10 +251,14 @@ __device__ __forceinline__ void load_voxel(const PassArgs& A, const GroupDev& g,
     dv.sig_dpar = 0.0f;
     dv.sig_dperp = 0.0f;
   }
-  const float dpar = LD ? x.dpar : A.model.d_par;
-  const float dperp = LD ? x.dperp : A.model.d_perp;
-  x.a1 = dpar * fin;
-  x.a2 = (dpar - dperp) * omf;
+  if (LD) {
+    x.a1 = x.dpar * fin;
+    x.a2 = (x.dpar - x.dperp) * omf;
+  } else {
+    // d E / d cs = -2 ln 2 cs (f_in e1 + (1 - Dperp/Dpar)(1 - f_in) e12)
+    x.a1 = -2.0f * kLn2 * fin;
+    x.a2 = -2.0f * kLn2 * (1.0f - A.model.d_perp / A.model.d_par) * omf;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,10 +308,11 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
                                      const float4 a, const float4 b, const float4 c, float inv_s2,
                                      float& t_loss, float& t_sig, float& sq, float& seed) {
   using AC = Acc<K, LD>;
+  // fixed D: (gx, gy, gz) = s g and cc = s cos (see stage_acquisition)
   const float gx = a.x, gy = a.y, gz = a.z;
-  const float kp = LD ? a.w * x.dpar : a.w;     // log2 e1 = kp cos^2
-  const float kq = LD ? b.x * x.dperp : b.x;    // log2 e12 = kq + (kp - kq) cos^2
-  const float kd = LD ? kp - kq : c.w;
+  const float kp = LD ? a.w * x.dpar : 0.0f;    // learned D: log2 e1 = kp cos^2
+  const float kq = LD ? b.x * x.dperp : b.x;    // log2 e12 = kq + kd cc^2
+  const float kd = LD ? kp - kq : c.z;
   float S = x.Fi[0] * b.y;
   S = fmaf(x.Fi[1], b.z, S);
   S = fmaf(x.Fi[2], b.w, S);
@@ -309,7 +321,7 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   for (int k = 0; k < K; ++k) {
     cc[k] = fmaf(gz, x.d[k][2], fmaf(gy, x.d[k][1], gx * x.d[k][0]));
     const float c2 = cc[k] * cc[k];
-    e1[k] = ex2(kp * c2);                 // exp(-b Dpar cos^2)
+    e1[k] = ex2(LD ? kp * c2 : -c2);      // exp(-b Dpar cos^2)
     e12[k] = ex2(fmaf(kd, c2, kq));       // exp(-b Dpar cos^2 - b Dperp sin^2)
     S = fmaf(x.Fa[k], e1[k], S);          // Eq. 3 with Eq. 5: F_k (f_in e1 + (1 - f_in) e12)
     S = fmaf(x.Fb[k], e12[k], S);
@@ -318,8 +330,10 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   sq = seed * S;
   // dS = dL/dS / B: the F_c carry B, so dS F_c is the adjoint of compartment c's signal
   const float dS = seed * c.x;
-  const float dSz = dS * c.z;             // dS (-2b), the factor of dE/dcos shared by the fibres
-  // from three fibres on, fold dS (-2b) into the two per-voxel factors once per pair
+  // the factor of the direction adjoint shared by the fibres: dS (-2b) (learned D),
+  // dS (fixed D: -2 ln2 is in a1, a2 and the scale s in cc and the staged vector)
+  const float dSz = LD ? dS * c.z : dS;
+  // from three fibres on, fold dSz into the two per-voxel factors once per pair
   // (two products) rather than into each fibre's cosine (one product per fibre)
   constexpr bool kFold = K >= 3;
   const float a1z = kFold ? x.a1 * dSz : x.a1, a2z = kFold ? x.a2 * dSz : x.a2;
@@ -330,8 +344,9 @@ __device__ __forceinline__ void pair(const Vox<K, LD>& x, Acc<K, LD>& acc, float
   for (int k = 0; k < K; ++k) {
     acc.r[AC::kE1 + k] = fmaf(dS, e1[k], acc.r[AC::kE1 + k]);
     acc.r[AC::kE12 + k] = fmaf(dS, e12[k], acc.r[AC::kE12 + k]);
-    // dE/dcos = -2b cos (Dpar f_in e1 + (Dpar - Dperp)(1 - f_in) e12), here times dS;
-    // the fibre's F_k multiplies the sums once per voxel, after the loop
+    // dE/dcos = -2b cos (Dpar f_in e1 + (Dpar - Dperp)(1 - f_in) e12), here times dS
+    // (fixed D: dE/dcs against the staged s g, the same product); the fibre's F_k
+    // multiplies the sums once per voxel, after the loop
     const float dc = (kFold ? cc[k] : cc[k] * dSz) * fmaf(a1z, e1[k], a2z * e12[k]);
     acc.r[AC::kGd + 3 * k + 0] = fmaf(dc, gx, acc.r[AC::kGd + 3 * k + 0]);
     acc.r[AC::kGd + 3 * k + 1] = fmaf(dc, gy, acc.r[AC::kGd + 3 * k + 1]);
@@ -1009,10 +1024,10 @@ __global__ __launch_bounds__(kBlock) void k_synth(PassArgs A) {
       for (int k = 0; k < K; ++k) {
         const float cc = fmaf(a.z, x.d[k][2], fmaf(a.y, x.d[k][1], a.x * x.d[k][0]));
         const float c2 = cc * cc;
-        const float kp = LD ? a.w * x.dpar : a.w;
+        const float kp = LD ? a.w * x.dpar : 0.0f;
         const float kq = LD ? b.x * x.dperp : b.x;
-        const float kd = LD ? kp - kq : c.w;
-        S = fmaf(x.Fa[k], ex2(kp * c2), S);
+        const float kd = LD ? kp - kq : c.z;
+        S = fmaf(x.Fa[k], ex2(LD ? kp * c2 : -c2), S);
         S = fmaf(x.Fb[k], ex2(fmaf(kd, c2, kq)), S);
       }
       out[(int64_t)n * V + v] = fmaf(c.x, S, c.y);

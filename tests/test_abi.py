@@ -117,6 +117,10 @@ def test_create_rejects_bad_acquisition_and_counts():
     m.s0_orphan = 0.0
     rc, msg = _create(model=m)
     assert rc == L.PRISM_E_INVALID and "s0_orphan" in msg
+    m = L.model_defaults()
+    m.d_par = 0.0
+    rc, msg = _create(model=m)
+    assert rc == L.PRISM_E_INVALID and "d_par" in msg
     lib = L.lib()
     assert lib.prism_problem_create(None, None, 0, None, 0, None) == L.PRISM_E_INVALID
     n = np.zeros(1025, dtype=np.float32)

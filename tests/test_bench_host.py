@@ -23,8 +23,8 @@ def test_roofline_unit_figures():
     K, N, P = 3, 288, 17
     # the fixed count of the method's steps: forward 10K + 8, adjoint 12K + 10
     assert bench.ALG_VALU_PER_PAIR == (10 * K + 8) + (12 * K + 10)
-    # the implementation's algebra: forward 8K + 3, data term 3, adjoint 8K + 8
-    assert bench.MIN_VALU_PER_PAIR == (8 * K + 3) + 3 + (8 * K + 8)
+    # the implementation's algebra: forward 7K + 3, data term 3, adjoint 8K + 7
+    assert bench.MIN_VALU_PER_PAIR == (7 * K + 3) + 3 + (8 * K + 7)
     assert bench.B0_VALU_PER_PAIR == 5
     assert bench.ALG_EXP_PER_PAIR == 2 * K
     # y, theta read, Adam moments read, theta and moments written
