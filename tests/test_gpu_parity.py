@@ -74,6 +74,23 @@ def test_ragged_masked_mixed_groups(launch):
     _check_groups("ragged", groups, launch=launch)
 
 
+@pytest.mark.parametrize("order", ["shells", "interleaved"])
+@pytest.mark.parametrize("launch", [None, dict(vox_per_lane=1, n_split=2, item_vox=128)])
+def test_mse_acquisition_order(order, launch):
+    """The same measurements shell by shell (the b = 0 ones first, which the
+    pass takes as whole b = 0 tiles) and in a random order (b = 0 measurements
+    scattered through the acquisition, every tile mixing shells), with the
+    range also split over two waves."""
+    g = masked_group(shape=(11, 9, 7), K=3, mode="mse", seed=21, acq_kind="three288", bias="poly2", fill=0.9)
+    if order == "interleaved":
+        perm = np.random.default_rng(3).permutation(g.acq.n)
+        acq = I.Acquisition(bval=g.acq.bval[perm], bvec=g.acq.bvec[perm], name="three288-interleaved")
+        th = dict(g.theta)
+        th["alpha"], th["beta"] = th["alpha"][perm], th["beta"][perm]
+        g = dataclasses.replace(g, acq=acq, y=np.ascontiguousarray(g.y[perm]), theta=th)
+    _check_groups(f"order={order}", [g], launch=launch)
+
+
 def test_many_items_per_group_and_ragged_tail():
     g = masked_group(shape=(23, 19, 17), K=3, mode="mse", seed=11, acq_kind="three288", bias="poly2", fill=0.8)
     _check_groups("multi-item", [g], launch=dict(vox_per_lane=1, n_split=2, item_vox=128))
