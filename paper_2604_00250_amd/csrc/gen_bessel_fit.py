@@ -172,6 +172,33 @@ def _estrin64(p, x):
     return lvl[0]
 
 
+def _estrin32(p, x, x2, x4, x8):
+    """Estrin's scheme in float32 (each step one FMA rounding), the kernels' order."""
+    lvl = [_fma32(p[2 * i + 1], x, p[2 * i]) if 2 * i + 1 < len(p) else np.full_like(x, p[2 * i])
+           for i in range((len(p) + 1) // 2)]
+    for xp in (x2, x4, x8):
+        if len(lvl) == 1:
+            break
+        lvl = [_fma32(lvl[2 * i + 1], xp, lvl[2 * i]) if 2 * i + 1 < len(lvl) else lvl[2 * i]
+               for i in range((len(lvl) + 1) // 2)]
+    return lvl[0]
+
+
+def _small_poly(c, x):
+    """sum_i c_i x^i for |x| <= 1 as the kernels take it: the four lowest terms in
+    float64, the rest (weight x^4, coefficients below 0.015) as a float32
+    polynomial with float32 coefficients, added in float64."""
+    c = np.asarray(c, np.float64)
+    x2 = x * x
+    low = (c[3] * x + c[2]) * x2 + (c[1] * x + c[0])
+    xf = x.astype(f32)
+    xf2 = f32(xf * xf)
+    xf4 = f32(xf2 * xf2)
+    xf8 = f32(xf4 * xf4)
+    hi = _estrin32(c[4:].astype(f32), xf, xf2, xf4, xf8)
+    return (x2 * x2) * hi.astype(np.float64) + low
+
+
 def _clenshaw64(c, x):
     x2 = x + x
     b1 = np.zeros_like(x)
@@ -193,8 +220,8 @@ def evaluate_f32(z, coefs=None):
     zd = z[s].astype(np.float64)
     t = zd * zd
     x = t * (2.0 / Z_SPLIT ** 2) - 1.0
-    G = _estrin64(np.asarray(cG, np.float64), x)
-    rho = _estrin64(np.asarray(cR, np.float64), x)
+    G = _small_poly(cG, x)
+    rho = _small_poly(cR, x)
     w = 1.0 - zd * rho
     omr[s] = w.astype(f32)
     q[s] = (2.0 * zd * w).astype(f32)
@@ -271,7 +298,8 @@ def main(out=None):
     f64s = lambda cs: ", ".join(f"{float(c)!r}" for c in cs)  # noqa: E731
     with open(out, "w") as f:
         f.write("// Generated by gen_bessel_fit.py -- do not edit.\n")
-        f.write("// Eq. 9 special functions.  z < 3.75 (float64): polynomials in x = 2t/3.75^2 - 1, t = z^2,\n")
+        f.write("// Eq. 9 special functions.  z < 3.75 (float64 with a float32 tail): polynomials in\n")
+        f.write("// x = 2t/3.75^2 - 1, t = z^2,\n")
         f.write("// lowest degree first, of G = log I0(z)/t (kSmallG) and rho = I1(z)/(z I0(z)) (kSmallRho).\n")
         f.write("// z >= 3.75 (float32): rational functions u P(x)/Q(x), x = 2u - 1, u = 3.75/z, of\n")
         f.write("// l = log(sqrt(2 pi z) I0e(z)) (kLargeLP / kLargeLQ) and d = 2z(1 - I1/I0) - 1\n")
@@ -284,10 +312,14 @@ def main(out=None):
         f.write(f"#define PRISM_LARGE_LP_N {len(cL[0])}\n#define PRISM_LARGE_LQ_N {len(cL[1])}\n")
         f.write(f"#define PRISM_LARGE_DP_N {len(cD[0])}\n#define PRISM_LARGE_DQ_N {len(cD[1])}\n")
         f.write(f"static constexpr float kBesselSplit = {Z_SPLIT!r}f;\n")
-        f.write("// in constant memory: the float64 branch reads them where it runs (as literals the\n")
-        f.write("// compiler keeps all of them in scalar registers across the measurement loop)\n")
+        f.write("// in constant memory: the float64 branch reads its four lowest coefficients where it\n")
+        f.write("// runs (as literals, the compiler would hold them in scalar registers across the\n")
+        f.write("// measurement loop); the higher ones, times x^4, are float32 literals (kSmallGHi,\n")
+        f.write("// kSmallRhoHi)\n")
         f.write(f"static __constant__ double kSmallG[PRISM_SMALL_G_N] = {{{f64s(cG)}}};\n")
         f.write(f"static __constant__ double kSmallRho[PRISM_SMALL_RHO_N] = {{{f64s(cR)}}};\n")
+        f.write(f"static constexpr float kSmallGHi[PRISM_SMALL_G_N - 4] = {{{f32s(cG[4:])}}};\n")
+        f.write(f"static constexpr float kSmallRhoHi[PRISM_SMALL_RHO_N - 4] = {{{f32s(cR[4:])}}};\n")
         f.write(f"static constexpr float kLargeLP[PRISM_LARGE_LP_N] = {{{f32s(cL[0])}}};\n")
         f.write(f"static constexpr float kLargeLQ[PRISM_LARGE_LQ_N] = {{{f32s(cL[1])}}};\n")
         f.write(f"static constexpr float kLargeDP[PRISM_LARGE_DP_N] = {{{f32s(cD[0])}}};\n")

@@ -236,40 +236,44 @@ __device__ __forceinline__ float horner(const float (&c)[N], float x) {
   return acc;
 }
 
-// Float64 polynomials over a table in constant memory (the small-argument
-// branch).  `c` is read where the branch runs: the table offset passes through
-// an empty asm statement there, so the compiler cannot hoist the 2N scalar
-// registers of the coefficients out of the measurement loop (float64 operands
-// cannot be instruction literals on this architecture).  Evaluated by Estrin's
-// scheme: coefficient pairs, then pairs of pairs with x^2, then with x^4 and
-// x^8 (the powers shared by the two small-argument polynomials), so the
-// longest chain of dependent float64 operations is about five instead of
-// N - 1: this branch runs for a few lanes of most waves, and its latency, not
-// its work, is what the measurement loop waits on.
-template <int N>
-__device__ __forceinline__ double estrin_d(const double* c, double x, double x2, double x4, double x8) {
-  static_assert(N >= 2 && N <= 16, "Estrin evaluation of degree 1..15");
+// The small-argument branch's polynomials sum_i c_i x^i, |x| <= 1: the four
+// lowest terms in float64 from a table in constant memory, the rest (weight
+// x^4, coefficients below 0.015) in float32 with the coefficients as
+// instruction literals, added in float64.  The float64 table is read where the
+// branch runs: its offset passes through an empty asm statement there, so the
+// compiler cannot hoist the coefficients' scalar registers out of the
+// measurement loop (float64 operands cannot be instruction literals on this
+// architecture).  The float32 part is evaluated by Estrin's scheme
+// (coefficient pairs, then pairs of pairs with x^2, x^4, x^8), so the longest
+// dependent chain is about five operations instead of N - 1: this branch runs
+// for a few lanes of most waves, and its latency, not its work, is what the
+// measurement loop waits on.
+__device__ __forceinline__ double low4_d(const double* c, double x, double x2) {
   int off = 0;
   asm volatile("" : "+s"(off));
   c += off;
+  return fma(fma(c[3], x, c[2]), x2, fma(c[1], x, c[0]));
+}
+template <int N>
+__device__ __forceinline__ float estrin_f(const float (&c)[N], float x, float x2, float x4, float x8) {
+  static_assert(N >= 2 && N <= 16, "Estrin evaluation of degree 1..15");
   constexpr int N1 = (N + 1) / 2, N2 = (N1 + 1) / 2, N3 = (N2 + 1) / 2;
-  double p1[N1], p2[N2], p3[N3];
+  float p1[N1], p2[N2], p3[N3];
 #pragma unroll
-  for (int i = 0; i < N1; ++i) p1[i] = 2 * i + 1 < N ? fma(c[2 * i + 1], x, c[2 * i]) : c[2 * i];
+  for (int i = 0; i < N1; ++i) p1[i] = 2 * i + 1 < N ? fmaf(c[2 * i + 1], x, c[2 * i]) : c[2 * i];
 #pragma unroll
-  for (int i = 0; i < N2; ++i) p2[i] = 2 * i + 1 < N1 ? fma(p1[2 * i + 1], x2, p1[2 * i]) : p1[2 * i];
+  for (int i = 0; i < N2; ++i) p2[i] = 2 * i + 1 < N1 ? fmaf(p1[2 * i + 1], x2, p1[2 * i]) : p1[2 * i];
 #pragma unroll
-  for (int i = 0; i < N3; ++i) p3[i] = 2 * i + 1 < N2 ? fma(p2[2 * i + 1], x4, p2[2 * i]) : p2[2 * i];
-  return N3 == 1 ? p3[0] : fma(p3[1], x8, p3[0]);
+  for (int i = 0; i < N3; ++i) p3[i] = 2 * i + 1 < N2 ? fmaf(p2[2 * i + 1], x4, p2[2 * i]) : p2[2 * i];
+  return N3 == 1 ? p3[0] : fmaf(p3[1], x8, p3[0]);
 }
 
 // Eq. 9 terms for z >= 0: returns log I0e(z) = log I0(z) - z and writes
 // 1 - R(z) (R = I1/I0) to omr and q = 2z (1 - R(z)) to q.  Each is within
-// 1.3e-7 relative of the exact value over [0, 1e5] (host emulation of this
+// 1.5e-7 relative of the exact value over [0, 1e5] (host emulation of this
 // algorithm; the tests measure the device).
-//   z < 3.75: float64 polynomials in t = z^2 (log I0(z) = t G(t),
-//             R(z) = z rho(t)), by Estrin's scheme, one rounding to float32
-//             per result;
+//   z < 3.75: polynomials in t = z^2 (log I0(z) = t G(t), R(z) = z rho(t)),
+//             float64 with a float32 tail, one rounding to float32 per result;
 //   z >= 3.75: float32 rational functions u P(x)/Q(x), x = 2u - 1, u = 3.75/z,
 //             of l = log(sqrt(2 pi z) I0e(z)) and d = q - 1 (for z > 2000 d is
 //             w/4 + w^2/4 + 25w^3/64, w = 1/z), so that
@@ -281,11 +285,14 @@ __device__ __forceinline__ float log_i0e(float z, float& omr, float& q) {
     // the two polynomials one after the other (one float64 accumulator live)
     const double zd = (double)z;
     const double x = fma(zd * zd, 2.0 / ((double)kBesselSplit * (double)kBesselSplit), -1.0);
-    const double x2 = x * x, x4 = x2 * x2, x8 = x4 * x4;
-    static_assert(PRISM_SMALL_G_N <= 16 && PRISM_SMALL_RHO_N <= 16 && PRISM_SMALL_G_N > 8 &&
-                  PRISM_SMALL_RHO_N > 8, "Estrin levels for the small-argument degrees");
-    const float li = (float)fma(zd * zd, estrin_d<PRISM_SMALL_G_N>(kSmallG, x, x2, x4, x8), -zd);
-    const double w = fma(-zd, estrin_d<PRISM_SMALL_RHO_N>(kSmallRho, x, x2, x4, x8), 1.0);
+    const double x2 = x * x, x4 = x2 * x2;
+    const float xf = (float)x, xf2 = xf * xf, xf4 = xf2 * xf2, xf8 = xf4 * xf4;
+    static_assert(PRISM_SMALL_G_N - 4 <= 16 && PRISM_SMALL_RHO_N - 4 <= 16 && PRISM_SMALL_G_N - 4 > 8 &&
+                  PRISM_SMALL_RHO_N - 4 > 8, "Estrin levels for the small-argument tails");
+    const double G = fma(x4, (double)estrin_f(kSmallGHi, xf, xf2, xf4, xf8), low4_d(kSmallG, x, x2));
+    const double rho = fma(x4, (double)estrin_f(kSmallRhoHi, xf, xf2, xf4, xf8), low4_d(kSmallRho, x, x2));
+    const float li = (float)fma(zd * zd, G, -zd);
+    const double w = fma(-zd, rho, 1.0);
     omr = (float)w;
     q = (float)(2.0 * zd * w);
     return li;
