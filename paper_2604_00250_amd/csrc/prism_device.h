@@ -280,23 +280,23 @@ __device__ __forceinline__ float estrin_f(const float (&c)[N], float x, float x2
 //             log I0e = (l - log(2 pi)/2) - log(z)/2, q = 1 + d and
 //             1 - R = d r + r with r = 1/(2z) from the hardware reciprocal
 //             refined by one Newton step.
-__device__ __forceinline__ float log_i0e(float z, float& omr, float& q) {
-  if (z < kBesselSplit) {
-    // the two polynomials one after the other (one float64 accumulator live)
-    const double zd = (double)z;
-    const double x = fma(zd * zd, 2.0 / ((double)kBesselSplit * (double)kBesselSplit), -1.0);
-    const double x2 = x * x, x4 = x2 * x2;
-    const float xf = (float)x, xf2 = xf * xf, xf4 = xf2 * xf2, xf8 = xf4 * xf4;
-    static_assert(PRISM_SMALL_G_N - 4 <= 16 && PRISM_SMALL_RHO_N - 4 <= 16 && PRISM_SMALL_G_N - 4 > 8 &&
-                  PRISM_SMALL_RHO_N - 4 > 8, "Estrin levels for the small-argument tails");
-    const double G = fma(x4, (double)estrin_f(kSmallGHi, xf, xf2, xf4, xf8), low4_d(kSmallG, x, x2));
-    const double rho = fma(x4, (double)estrin_f(kSmallRhoHi, xf, xf2, xf4, xf8), low4_d(kSmallRho, x, x2));
-    const float li = (float)fma(zd * zd, G, -zd);
-    const double w = fma(-zd, rho, 1.0);
-    omr = (float)w;
-    q = (float)(2.0 * zd * w);
-    return li;
-  }
+// the branch below the split (z < kBesselSplit)
+__device__ __forceinline__ float log_i0e_small(float z, float& omr, float& q) {
+  const double zd = (double)z;
+  const double x = fma(zd * zd, 2.0 / ((double)kBesselSplit * (double)kBesselSplit), -1.0);
+  const double x2 = x * x, x4 = x2 * x2;
+  const float xf = (float)x, xf2 = xf * xf, xf4 = xf2 * xf2, xf8 = xf4 * xf4;
+  static_assert(PRISM_SMALL_G_N - 4 <= 16 && PRISM_SMALL_RHO_N - 4 <= 16 && PRISM_SMALL_G_N - 4 > 8 &&
+                PRISM_SMALL_RHO_N - 4 > 8, "Estrin levels for the small-argument tails");
+  const double G = fma(x4, (double)estrin_f(kSmallGHi, xf, xf2, xf4, xf8), low4_d(kSmallG, x, x2));
+  const double rho = fma(x4, (double)estrin_f(kSmallRhoHi, xf, xf2, xf4, xf8), low4_d(kSmallRho, x, x2));
+  const double w = fma(-zd, rho, 1.0);
+  omr = (float)w;
+  q = (float)(2.0 * zd * w);
+  return (float)fma(zd * zd, G, -zd);
+}
+// the branch from the split up (z >= kBesselSplit)
+__device__ __forceinline__ float log_i0e_large(float z, float& omr, float& q) {
   const float iz0 = rcp(z);
   const float iz = fmaf(fmaf(-z, iz0, 1.0f), iz0, iz0);
   const float x = fmaf(2.0f * kBesselSplit, iz, -1.0f);
@@ -310,6 +310,12 @@ __device__ __forceinline__ float log_i0e(float z, float& omr, float& q) {
   omr = fmaf(d, r, r);
   q = 1.0f + d;
   return fmaf(-kHalfLn2, lg2(z), l - kHalfLog2Pi);
+}
+// (a branch per lane: computing both for every lane and selecting, so that the
+// two dependent chains overlap, measured slower)
+__device__ __forceinline__ float log_i0e(float z, float& omr, float& q) {
+  if (z < kBesselSplit) return log_i0e_small(z, omr, q);
+  return log_i0e_large(z, omr, q);
 }
 
 }  // namespace prism
