@@ -95,13 +95,6 @@ __device__ __forceinline__ float dpp_f32(float x) {
                                          false));
 }
 
-// row_shr:1 within each row of 16 lanes, the row's first lane reading 0 (bound
-// control set: no separate "old" operand has to be written first)
-__device__ __forceinline__ float row_shr1_zero(float x) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x111, 0xf, 0xf, true));
-}
-
 // Per-measurement sums over each row of 16 lanes, fed one value per lane per
 // measurement in groups of four (measurement t = 4g + u of a tile of 16):
 // afterwards lane l of a row holds the row's sum for measurement
@@ -157,23 +150,6 @@ __device__ __forceinline__ void row_scatter_group(RowScatter& s, bool here) {
   float t = s.q + dpp_f32<0x141>(s.q);  // row_half_mirror: lane xor 7
   t += dpp_f32<0x140>(t);               // row_mirror: lane xor 15
   s.acc = here ? t : s.acc;
-}
-
-// Sum over the 64 lanes of a wave; the total lands in lane 63 (other lanes hold
-// partial sums).  quad_perm xor 1, xor 2, half-row mirror, row mirror, then
-// the two row broadcasts that chain rows 0-3.
-__device__ __forceinline__ float wave_sum_to_63(float x) {
-  x += dpp_f32<0xB1>(x);              // quad_perm [1,0,3,2]
-  x += dpp_f32<0x4E>(x);              // quad_perm [2,3,0,1]
-  x += dpp_f32<0x141>(x);             // row_half_mirror
-  x += dpp_f32<0x140>(x);             // row_mirror
-  x += dpp_f32<0x142, 0xA>(x);        // row_bcast:15 into rows 1 and 3
-  x += dpp_f32<0x143, 0xC>(x);        // row_bcast:31 into rows 2 and 3
-  return x;
-}
-
-__device__ __forceinline__ float lane63(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
 }
 
 // Lane exchanges across rows without per-use index arithmetic: ds_swizzle in
