@@ -176,12 +176,15 @@ typedef struct {
                            one block chunk (that multiple) with a fixed n_split, else
                            about six blocks per compute unit over the problem */
   int32_t persistent;   /* 0: one launch per kernel variant (K, mode, learned D,
-                           voxels per lane); 1: one persistent launch over all work
-                           items, largest first, each block popping items from a
-                           device counter */
-  int32_t max_blocks;   /* persistent launch: at most this many blocks (0 = as many
-                           as the device holds at once); fewer blocks than work items
-                           make each block run several items in turn */
+                           voxels per lane); 1: persistent launches over all work
+                           items, one per register class (K <= 2, compiled for three
+                           waves per SIMD; K >= 3, for two), each over its items
+                           largest first, each block popping items from a device
+                           counter of its launch */
+  int32_t max_blocks;   /* persistent launches: at most this many blocks together,
+                           shared out by work (0 = as many as the device holds at
+                           once; at least one per launch); fewer blocks than work
+                           items make each block run several items in turn */
   int32_t stagger;      /* 1 (the default): a problem of one large group cut into
                            one-chunk items (vox_per_lane 1, n_split 1, item_vox 0)
                            starts every XCD's run of items with CUs/8 shorter items
@@ -192,8 +195,9 @@ typedef struct {
                            where it does not apply (several groups, other shapes,
                            fewer than two rounds of blocks, or when the measurement
                            split's LDS would cost the variant a block per CU). */
-  int32_t concurrent;   /* 1 (the default): a plan of one launch per kernel variant
-                           (persistent 0) with several variants runs them on up to
+  int32_t concurrent;   /* 1 (the default): a plan of several fused-pass launches
+                           (one per kernel variant, or the persistent launches of
+                           two register classes) runs them on up to
                            four streams at once -- the caller's and three the
                            problem owns (default priority) -- forked from and
                            joined back into the caller's stream with events, so
@@ -243,8 +247,8 @@ int32_t prism_problem_launch(const prism_problem* h, prism_launch* launch);
  * which the first min(cap, *n) are written to out (host memory). */
 int32_t prism_problem_buckets(const prism_problem* h, prism_bucket_launch* out, int32_t cap,
                               int32_t* n);
-/* The current plan: work items, fused-pass launches per call, and the grid of
- * the persistent launch (0 when the plan is not persistent). */
+/* The current plan: work items, fused-pass launches per call, and the blocks of
+ * the persistent launches together (0 when the plan is not persistent). */
 int32_t prism_problem_plan_info(const prism_problem* h, int32_t* n_items, int32_t* n_launches,
                                 int32_t* persistent_blocks);
 /* Hash of the sources the library was built from (a NUL-terminated string

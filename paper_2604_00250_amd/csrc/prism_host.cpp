@@ -57,6 +57,8 @@ struct Bucket {
   int xsplit;  // cross-wave buffer rows the launch needs
   int vpl;     // voxels per lane of the launch (1 for the persistent launch)
   int stream;  // 0: the caller's stream; s > 0: the problem's side stream s - 1
+  int cls;     // persistent launch: register class of its items (persistent_class)
+  int grid;    // persistent launch: blocks
 };
 
 constexpr int kSideStreams = 3;  // with the caller's: the four hardware queues a process gets
@@ -286,16 +288,20 @@ int plan(prism_problem* h) {
   std::vector<ItemDev> ordered;
   ordered.reserve(items.size());
   if (L.persistent) {
-    // one launch; items largest first (LPT)
-    ordered = items;
-    std::stable_sort(ordered.begin(), ordered.end(),
-                     [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
-    Bucket b{0, 0, 0, 0, 0, (int)ordered.size(), 0, 1};
-    for (const ItemDev& it : ordered) {
-      b.maxN = std::max(b.maxN, h->groups[it.group].N);
-      b.xsplit = std::max(b.xsplit, xsplit_of(it.n_split));
+    // one launch per register class; items largest first (LPT) within each
+    for (int cls = 0; cls < 2; ++cls) {
+      Bucket b{0, 0, 0, 0, (int)ordered.size(), 0, 0, 1, 0, cls, 0};
+      for (const ItemDev& it : items)
+        if (persistent_class(h->groups[it.group].K) == cls) ordered.push_back(it);
+      std::stable_sort(ordered.begin() + b.item_begin, ordered.end(),
+                       [&](const ItemDev& a, const ItemDev& c) { return cost(a) > cost(c); });
+      b.item_count = (int)ordered.size() - b.item_begin;
+      for (int i = b.item_begin; i < (int)ordered.size(); ++i) {
+        b.maxN = std::max(b.maxN, h->groups[ordered[i].group].N);
+        b.xsplit = std::max(b.xsplit, xsplit_of(ordered[i].n_split));
+      }
+      if (b.item_count > 0) buckets.push_back(b);
     }
-    if (b.item_count > 0) buckets.push_back(b);
   } else {
     // one launch per kernel variant (K, mode, learned D, voxels per lane); items
     // inside a launch largest first (LPT)
@@ -323,7 +329,7 @@ int plan(prism_problem* h) {
   // concurrent variant launches: each launch to the stream with the least work so
   // far, largest launch first (the caller's stream takes the first)
   int n_side = 0;
-  if (!L.persistent && L.concurrent && buckets.size() > 1) {
+  if (L.concurrent && buckets.size() > 1) {
     n_side = std::min<int>(kSideStreams, (int)buckets.size() - 1);
     std::vector<int64_t> work(buckets.size(), 0);
     for (size_t b = 0; b < buckets.size(); ++b)
@@ -388,14 +394,34 @@ int plan(prism_problem* h) {
   h->ws_rec = (size_t)rec_off;
   h->ws_part = tiles.size() * 64;
   h->persistent_grid = 0;
-  if (L.persistent && !buckets.empty()) {
+  if (L.persistent && !h->buckets.empty()) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
       cus = 256;
-    const int bpc = persistent_blocks_per_cu(buckets[0].maxN, buckets[0].xsplit);
-    int grid = std::min((int)ordered.size(), cus * bpc);
-    if (L.max_blocks > 0) grid = std::min(grid, L.max_blocks);
-    h->persistent_grid = std::max(1, grid);
+    // max_blocks caps the launches' blocks together, shared out by work
+    int64_t total = 0;
+    std::vector<int64_t> work(h->buckets.size(), 0);
+    for (size_t bi = 0; bi < h->buckets.size(); ++bi) {
+      const Bucket& b = h->buckets[bi];
+      for (int i = b.item_begin; i < b.item_begin + b.item_count; ++i) work[bi] += cost(ordered[i]);
+      total += work[bi];
+    }
+    int left = L.max_blocks;
+    for (size_t bi = 0; bi < h->buckets.size(); ++bi) {
+      Bucket& b = h->buckets[bi];
+      const int bpc = persistent_blocks_per_cu(b.cls, b.maxN, b.xsplit);
+      int grid = std::min(b.item_count, cus * bpc);
+      if (L.max_blocks > 0) {
+        const int rest = (int)(h->buckets.size() - bi - 1);
+        const int share = bi + 1 == h->buckets.size()
+                              ? left
+                              : (int)std::max<int64_t>(1, (int64_t)L.max_blocks * work[bi] / std::max<int64_t>(total, 1));
+        grid = std::min(grid, std::max(1, std::min(share, left - rest)));
+        left -= grid;
+      }
+      b.grid = std::max(1, grid);
+      h->persistent_grid += b.grid;
+    }
   }
   hipError_t e = upload(&h->d_items, h->items);
   if (e == hipSuccess) e = upload(&h->d_tiles, h->tiles);
@@ -964,7 +990,7 @@ int run_pass(const prism_problem* h, const float* y, const float* theta_micro, c
     const bool timed = h->prof && bs == s && h->ev_used + 2 <= (int)h->ev.size();
     if (timed) (void)hipEventRecord(h->ev[h->ev_used], s);
     if (h->launch.persistent)
-      e = launch_pass_persistent(a, b.maxN, h->persistent_grid, counter, bs);
+      e = launch_pass_persistent(a, b.cls, b.maxN, b.grid, counter + 32 * b.cls, bs);
     else
       e = launch_pass_maxn(a, b.K, b.mode, b.learn_d, b.vpl, b.maxN, bs);
     if (e != hipSuccess) return hip_fail(e, "fused-pass launch");

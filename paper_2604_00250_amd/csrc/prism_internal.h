@@ -170,9 +170,11 @@ struct StitchArgs {
 // max_nv: voxels of the largest work item
 hipError_t launch_spatial(const PassArgs& a, int n_items, int spatial_c, int max_nv, hipStream_t s);
 hipError_t launch_stage(const PassArgs& a, int n_groups, hipStream_t s);
-hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
+// persistent launch of one register class (persistent_class(K) of its items)
+int persistent_class(int K);
+hipError_t launch_pass_persistent(const PassArgs& a, int cls, int maxN, int grid, int32_t* counter,
                                   hipStream_t s);
-int persistent_blocks_per_cu(int maxN, int xsplit);
+int persistent_blocks_per_cu(int cls, int maxN, int xsplit);
 // launch facts of the fused pass's per-variant kernels: LDS bytes per block (static
 // and dynamic) and the waves per SIMD its register budget allows
 size_t pass_lds_per_block(int maxN, int xsplit, int K, int learn_d, int vpl);

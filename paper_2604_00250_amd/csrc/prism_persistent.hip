@@ -27,9 +27,10 @@ __device__ __forceinline__ void dispatch_item(const PassArgs& A, const float4* _
   }
 }
 
-__global__ __launch_bounds__(kBlock, PRISM_PERSISTENT_MIN_WAVES) void k_pass_persistent(PassArgs A,
-                                                            const float4* __restrict__ acq_global,
-                                                            int32_t* counter) {
+// KLO..KHI: the fibre counts the launch's items may have (one register class)
+template <int KLO, int KHI, int MINW>
+__global__ __launch_bounds__(kBlock, MINW) void k_pass_persistent(PassArgs A, const float4* __restrict__ acq_global,
+                                                                  int32_t* counter) {
   extern __shared__ float4 smem4[];
   __shared__ PassShared sh;
   __shared__ int next;
@@ -41,41 +42,52 @@ __global__ __launch_bounds__(kBlock, PRISM_PERSISTENT_MIN_WAVES) void k_pass_per
     if (i >= A.n_items) break;
     const ItemDev it = A.items[A.item_base + i];
     switch ((it.kind >> 2) + 1) {
-      case 1: dispatch_item<1>(A, acq_global, it, smem4, sh); break;
-      case 2: dispatch_item<2>(A, acq_global, it, smem4, sh); break;
-      case 3: dispatch_item<3>(A, acq_global, it, smem4, sh); break;
-      case 4: dispatch_item<4>(A, acq_global, it, smem4, sh); break;
-      case 5: dispatch_item<5>(A, acq_global, it, smem4, sh); break;
-      default: dispatch_item<6>(A, acq_global, it, smem4, sh); break;
+      case 1: if (KLO <= 1 && 1 <= KHI) dispatch_item<1>(A, acq_global, it, smem4, sh); break;
+      case 2: if (KLO <= 2 && 2 <= KHI) dispatch_item<2>(A, acq_global, it, smem4, sh); break;
+      case 3: if (KLO <= 3 && 3 <= KHI) dispatch_item<3>(A, acq_global, it, smem4, sh); break;
+      case 4: if (KLO <= 4 && 4 <= KHI) dispatch_item<4>(A, acq_global, it, smem4, sh); break;
+      case 5: if (KLO <= 5 && 5 <= KHI) dispatch_item<5>(A, acq_global, it, smem4, sh); break;
+      default: if (KLO <= 6 && 6 <= KHI) dispatch_item<6>(A, acq_global, it, smem4, sh); break;
     }
   }
 }
-
 __global__ void k_counter_reset(int32_t* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
 
-hipError_t launch_pass_persistent(const PassArgs& a, int maxN, int grid, int32_t* counter,
+// The two register classes of the persistent launch: items with K <= 3 in a
+// kernel held to three waves per SIMD, K >= 4 in one held to two (one kernel
+// for all would hold every item to the largest variant's registers).
+int persistent_class(int K) { return K <= 2 ? 0 : 1; }
+
+hipError_t launch_pass_persistent(const PassArgs& a, int cls, int maxN, int grid, int32_t* counter,
                                   hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   const size_t lds = pass_lds_bytes(maxN, a.n_split, acc_count(kMaxK, true), 1);
+  const void* fn = cls == 0 ? (const void*)k_pass_persistent<1, 2, 3>
+                            : (const void*)k_pass_persistent<3, kMaxK, PRISM_PERSISTENT_MIN_WAVES>;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pass_persistent,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_counter_reset, dim3(1), dim3(64), 0, s, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pass_persistent, dim3(grid), dim3(kBlock), lds, s, a,
-                     reinterpret_cast<const float4*>(a.wsp), counter);
+  if (cls == 0)
+    hipLaunchKernelGGL((k_pass_persistent<1, 2, 3>), dim3(grid), dim3(kBlock), lds, s, a,
+                       reinterpret_cast<const float4*>(a.wsp), counter);
+  else
+    hipLaunchKernelGGL((k_pass_persistent<3, kMaxK, PRISM_PERSISTENT_MIN_WAVES>), dim3(grid), dim3(kBlock), lds, s,
+                       a, reinterpret_cast<const float4*>(a.wsp), counter);
   return hipGetLastError();
 }
 
-int persistent_blocks_per_cu(int maxN, int xsplit) {
+int persistent_blocks_per_cu(int cls, int maxN, int xsplit) {
   const size_t lds = pass_lds_bytes(maxN, xsplit, acc_count(kMaxK, true), 1);
+  const void* fn = cls == 0 ? (const void*)k_pass_persistent<1, 2, 3>
+                            : (const void*)k_pass_persistent<3, kMaxK, PRISM_PERSISTENT_MIN_WAVES>;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_pass_persistent, kBlock, lds) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
